@@ -1,0 +1,456 @@
+/*
+ * Plain FP64 CPU oracle for one step of multi-channel Lenia with localized
+ * growth genes, and for that step's vector-Jacobian product.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code with
+ * the HIP library and is written from the paper's definitions, not for speed:
+ * the convolution is the direct spatial sum over kernel taps on the torus
+ * (the paper's FFT route reaches the same result up to rounding).
+ *
+ * Definitions followed (Chan 2023, "Towards Large-Scale Simulations of
+ * Open-Ended Evolution in Continuous Cellular Automata"):
+ *   - Section 2.1 / Algorithm 1: normalized kernels K~ = K / sum(K), update
+ *     A <- clip01(A + sum_k G_k(K~_k * A)), clip [x]_a^b = max(min(x,b),a);
+ *   - Section 2.2: Delta masks with cutoff eps, alpha = Delta_all(U) and
+ *     Delta_all(P), P <- P (.) alpha;
+ *   - Section 2.3: P <- clip01((P * K_diff) / (Delta_same(P) * K_diff)) with a
+ *     disk K_diff of radius r_diff;
+ *   - Section 2.4: growth read from the local genes (m, s, h) of kernel k;
+ *   - Algorithm 2: order diffuse -> convolve -> alpha -> mask -> grow/update.
+ * Readings where the paper is silent or its printed form is contradicted by its
+ * own behaviour (all listed with reasons in the design notes):
+ *   - kernel shell: K(D) = beta_i * exp(4 - 1/(r(1-r))), D = |d|/R < 1,
+ *     i = floor(B*D), r = B*D - i (classic Lenia ring shell, cited by the paper);
+ *   - growth G(u; m,s,h) = h * (2 exp(-(u-m)^2 / (2 s^2)) - 1);
+ *   - update with a time step: A' = clip01(A + dt * sum_k g_k), ascending k;
+ *   - U in the alpha mask is the normalized potential u_k = K~_k * A;
+ *   - diffusion disk |d| <= r_diff inclusive; output 0 where the count is 0;
+ *   - thresholds are strict (> eps); only the m, s, h genes are localized.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_EXPORT __attribute__((visibility("default")))
+
+static double core_fn(double r)
+{
+    if (r <= 0.0 || r >= 1.0) return 0.0;
+    return exp(4.0 - 1.0 / (r * (1.0 - r)));
+}
+
+/* Shell index and shell-local radius of offset (dy,dx); returns -1 outside the
+ * open disk |d| < R. */
+static int shell_of(int R, int B, int dy, int dx, double* r_local)
+{
+    long d2 = (long)dy * dy + (long)dx * dx;
+    if (d2 >= (long)R * R) return -1;
+    double BD = (double)B * sqrt((double)d2) / (double)R;
+    int i = (int)floor(BD);
+    if (i >= B) return -1;
+    *r_local = BD - (double)i;
+    return i;
+}
+
+/* Unnormalized shell basis S_i(d) (the core evaluated in shell i, 0 elsewhere). */
+ORACLE_EXPORT double oracle_shell_basis(int R, int B, int i, int dy, int dx)
+{
+    double r = 0.0;
+    int s = shell_of(R, B, dy, dx, &r);
+    return (s == i) ? core_fn(r) : 0.0;
+}
+
+/* Normalized kernel K~ on the (2R+1)x(2R+1) offset grid, index
+ * [(dy+R)*(2R+1) + (dx+R)].  Returns the normalizer Z = sum of the raw kernel
+ * (0 if the kernel is identically zero, in which case K is left zero). */
+ORACLE_EXPORT double oracle_kernel(int R, int B, const double* beta, double* K)
+{
+    int S = 2 * R + 1;
+    double Z = 0.0;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            double v = 0.0;
+            for (int i = 0; i < B; ++i) v += beta[i] * oracle_shell_basis(R, B, i, dy, dx);
+            K[(dy + R) * S + (dx + R)] = v;
+            Z += v;
+        }
+    if (Z == 0.0) return 0.0;
+    for (int t = 0; t < S * S; ++t) K[t] /= Z;
+    return Z;
+}
+
+static inline long wrap(long i, long n)
+{
+    long r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Forward internals of one step at every cell, shared by step and VJP. */
+typedef struct {
+    int H, W, C, NK, R, localized, genotype_update, r_diff;
+    const int *src, *dst;
+    const double* K;        /* NK * (2R+1)^2 */
+    double dt, eps, tau;
+    const double *gm, *gs, *gh;
+    const double *A, *P;
+    /* outputs of the forward pass */
+    double* num;            /* 3*NK*H*W (diffusion numerator)   */
+    double* cnt;            /* 3*NK*H*W (diffusion count n)      */
+    double* Pd;             /* 3*NK*H*W diffused genes (or P)    */
+    double* U;              /* NK*H*W potentials                 */
+    uint8_t* alpha;         /* H*W                               */
+    double* Z;              /* C*H*W pre-clip update             */
+} fwd_t;
+
+static void forward_internals(fwd_t* f)
+{
+    const long N = (long)f->H * f->W;
+    const int S = 2 * f->R + 1;
+    const int NP = 3 * f->NK;
+
+    /* Section 2.3: diffusion of every gene plane (only when genes are updated). */
+    if (f->localized) {
+        if (f->genotype_update) {
+            int rd = f->r_diff;
+            #pragma omp parallel for schedule(static)
+            for (long y = 0; y < f->H; ++y)
+                for (int pk = 0; pk < NP; ++pk)
+                    for (long x = 0; x < f->W; ++x) {
+                        double num = 0.0, n = 0.0;
+                        for (int dy = -rd; dy <= rd; ++dy)
+                            for (int dx = -rd; dx <= rd; ++dx) {
+                                if (dy * dy + dx * dx > rd * rd) continue;
+                                double v = f->P[(long)pk * N + wrap(y + dy, f->H) * f->W + wrap(x + dx, f->W)];
+                                num += v;
+                                if (v > f->eps) n += 1.0;
+                            }
+                        long o = (long)pk * N + y * f->W + x;
+                        f->num[o] = num;
+                        f->cnt[o] = n;
+                        double q = (n > 0.0) ? num / n : 0.0;
+                        f->Pd[o] = (n > 0.0) ? fmax(fmin(q, 1.0), 0.0) : 0.0;
+                    }
+        } else {
+            memcpy(f->Pd, f->P, sizeof(double) * NP * N);
+        }
+    }
+
+    /* Potentials u_k(x) = sum_d K~_k(d) A_src(x + d), direct torus sum. */
+    #pragma omp parallel for schedule(static)
+    for (long y = 0; y < f->H; ++y)
+        for (int k = 0; k < f->NK; ++k) {
+            const double* Ks = f->K + (long)k * S * S;
+            const double* As = f->A + (long)f->src[k] * N;
+            for (long x = 0; x < f->W; ++x) {
+                double u = 0.0;
+                for (int dy = -f->R; dy <= f->R; ++dy) {
+                    const double* row = As + wrap(y + dy, f->H) * f->W;
+                    const double* krow = Ks + (long)(dy + f->R) * S + f->R;
+                    for (int dx = -f->R; dx <= f->R; ++dx) {
+                        double kv = krow[dx];
+                        if (kv != 0.0) u += kv * row[wrap(x + dx, f->W)];
+                    }
+                }
+                f->U[(long)k * N + y * f->W + x] = u;
+            }
+        }
+
+    /* Section 2.2 alpha mask and Algorithm 2 growth / update. */
+    #pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c) {
+        int a = 1;
+        if (f->localized && f->genotype_update) {
+            for (int k = 0; k < f->NK; ++k) if (!(f->U[(long)k * N + c] > f->eps)) a = 0;
+            for (int pk = 0; pk < NP; ++pk) if (!(f->Pd[(long)pk * N + c] > f->eps)) a = 0;
+        }
+        f->alpha[c] = (uint8_t)a;
+        for (int ch = 0; ch < f->C; ++ch) {
+            double sum = 0.0;
+            for (int k = 0; k < f->NK; ++k) {
+                if (f->dst[k] != ch) continue;
+                double g = 0.0;
+                if (a) {
+                    double m, s, h;
+                    if (f->localized) {
+                        m = f->Pd[(long)(0 * f->NK + k) * N + c];
+                        s = f->Pd[(long)(1 * f->NK + k) * N + c];
+                        h = f->Pd[(long)(2 * f->NK + k) * N + c];
+                    } else {
+                        m = f->gm[k]; s = f->gs[k]; h = f->gh[k];
+                    }
+                    double d = f->U[(long)k * N + c] - m;
+                    g = h * (2.0 * exp(-d * d / (2.0 * s * s)) - 1.0);
+                }
+                sum += g;
+            }
+            f->Z[(long)ch * N + c] = f->A[(long)ch * N + c] + f->dt * sum;
+        }
+    }
+}
+
+static int alloc_fwd(fwd_t* f)
+{
+    const long N = (long)f->H * f->W;
+    const long NPN = 3L * f->NK * N;
+    f->num = f->cnt = f->Pd = NULL;
+    if (f->localized) {
+        f->num = (double*)calloc(NPN, sizeof(double));
+        f->cnt = (double*)calloc(NPN, sizeof(double));
+        f->Pd = (double*)calloc(NPN, sizeof(double));
+    }
+    f->U = (double*)calloc((long)f->NK * N, sizeof(double));
+    f->alpha = (uint8_t*)calloc(N, 1);
+    f->Z = (double*)calloc((long)f->C * N, sizeof(double));
+    if (!f->U || !f->alpha || !f->Z || (f->localized && (!f->num || !f->cnt || !f->Pd))) return -1;
+    return 0;
+}
+
+static void free_fwd(fwd_t* f)
+{
+    free(f->num); free(f->cnt); free(f->Pd); free(f->U); free(f->alpha); free(f->Z);
+}
+
+/* Ambiguity bits per cell: bit 0 = a thresholded quantity (u_k or diffused
+ * gene) lies within tau of eps, so either branch of alpha is correct; bit 1 =
+ * a clipped quantity (pre-clip update z, diffusion quotient q) lies within tau
+ * of a clip bound, so either side of the subgradient is correct. */
+static void ambiguity(const fwd_t* f, uint8_t* amb)
+{
+    const long N = (long)f->H * f->W;
+    const int NP = 3 * f->NK;
+    #pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c) {
+        uint8_t b = 0;
+        if (f->localized && f->genotype_update) {
+            for (int k = 0; k < f->NK; ++k)
+                if (fabs(f->U[(long)k * N + c] - f->eps) <= f->tau) b |= 1;
+            for (int pk = 0; pk < NP; ++pk)
+                if (fabs(f->Pd[(long)pk * N + c] - f->eps) <= f->tau) b |= 1;
+            for (int pk = 0; pk < NP; ++pk) {
+                double n = f->cnt[(long)pk * N + c];
+                if (n > 0.0) {
+                    double q = f->num[(long)pk * N + c] / n;
+                    if (fabs(q) <= f->tau || fabs(q - 1.0) <= f->tau) b |= 2;
+                }
+            }
+        }
+        for (int ch = 0; ch < f->C; ++ch) {
+            double z = f->Z[(long)ch * N + c];
+            if (fabs(z) <= f->tau || fabs(z - 1.0) <= f->tau) b |= 2;
+        }
+        amb[c] = b;
+    }
+}
+
+/*
+ * One step.  Arrays are row-major: A[C][H][W], P[3][NK][H][W] (planes m, s, h,
+ * each ordered by kernel), K[NK][(2R+1)^2] normalized kernels.
+ * Outputs: A_out, P_out (P_out ignored when not localized); optional U_out
+ * [NK][H][W], alpha_out [H][W], amb_out [H][W] (may be NULL).
+ * Returns 0 on success, -1 on allocation failure.
+ */
+ORACLE_EXPORT int oracle_step(int H, int W, int C, int NK, const int* src, const int* dst,
+                              int R, const double* K, double dt, int localized,
+                              const double* gm, const double* gs, const double* gh,
+                              int genotype_update, double eps, int r_diff, double tau,
+                              const double* A, const double* P,
+                              double* A_out, double* P_out, double* U_out,
+                              uint8_t* alpha_out, uint8_t* amb_out)
+{
+    fwd_t f = {H, W, C, NK, R, localized, localized ? genotype_update : 0, r_diff,
+               src, dst, K, dt, eps, tau, gm, gs, gh, A, P};
+    if (alloc_fwd(&f)) { free_fwd(&f); return -1; }
+    forward_internals(&f);
+    const long N = (long)H * W;
+    for (long i = 0; i < (long)C * N; ++i) A_out[i] = fmax(fmin(f.Z[i], 1.0), 0.0);
+    if (localized && P_out) {
+        for (long pk = 0; pk < 3L * NK; ++pk)
+            for (long c = 0; c < N; ++c)
+                P_out[pk * N + c] = f.genotype_update ? (f.alpha[c] ? f.Pd[pk * N + c] : 0.0)
+                                                      : P[pk * N + c];
+    }
+    if (U_out) memcpy(U_out, f.U, sizeof(double) * NK * N);
+    if (alpha_out) memcpy(alpha_out, f.alpha, N);
+    if (amb_out) ambiguity(&f, amb_out);
+    free_fwd(&f);
+    return 0;
+}
+
+/*
+ * Vector-Jacobian product of one step.  Given the cotangents gA_next [C][H][W]
+ * and gP_next [3][NK][H][W] of (A', P'), returns
+ *   gA [C][H][W]      d<gA',A'> + <gP',P'> / dA
+ *   gP [3][NK][H][W]  ... / dP                       (localized only)
+ *   gK [NK][(2R+1)^2] ... / dK~ (normalized kernel taps)
+ *   gm, gs, gh [NK]   ... / d(global genes)           (global mode only)
+ * Piecewise-constant parts (alpha, the diffusion count n) carry no gradient;
+ * clips use the inclusive subgradient [lo <= x <= hi].
+ */
+ORACLE_EXPORT int oracle_step_vjp(int H, int W, int C, int NK, const int* src, const int* dst,
+                                  int R, const double* K, double dt, int localized,
+                                  const double* gm_in, const double* gs_in, const double* gh_in,
+                                  int genotype_update, double eps, int r_diff, double tau,
+                                  const double* A, const double* P,
+                                  const double* gA_next, const double* gP_next,
+                                  double* gA, double* gP, double* gK,
+                                  double* gm, double* gs, double* gh, uint8_t* amb_out)
+{
+    fwd_t f = {H, W, C, NK, R, localized, localized ? genotype_update : 0, r_diff,
+               src, dst, K, dt, eps, tau, gm_in, gs_in, gh_in, A, P};
+    if (alloc_fwd(&f)) { free_fwd(&f); return -1; }
+    forward_internals(&f);
+    const long N = (long)H * W;
+    const int S = 2 * R + 1;
+    const int NP = 3 * NK;
+
+    double* zbar = (double*)calloc((long)C * N, sizeof(double));
+    double* ubar = (double*)calloc((long)NK * N, sizeof(double));
+    double* gPd = localized ? (double*)calloc((long)NP * N, sizeof(double)) : NULL;
+    if (!zbar || !ubar || (localized && !gPd)) {
+        free(zbar); free(ubar); free(gPd); free_fwd(&f); return -1;
+    }
+
+    /* clip of the state update (inclusive subgradient) */
+    for (long i = 0; i < (long)C * N; ++i) {
+        double z = f.Z[i];
+        zbar[i] = (z >= 0.0 && z <= 1.0) ? gA_next[i] : 0.0;
+        gA[i] = zbar[i];
+    }
+    if (!localized)
+        for (int k = 0; k < NK; ++k) { gm[k] = 0.0; gs[k] = 0.0; gh[k] = 0.0; }
+
+    /* growth derivatives */
+    for (int k = 0; k < NK; ++k) {
+        double am = 0.0, as = 0.0, ah = 0.0;
+        for (long c = 0; c < N; ++c) {
+            if (!f.alpha[c]) continue;
+            double m, s, h;
+            if (localized) {
+                m = f.Pd[(long)(0 * NK + k) * N + c];
+                s = f.Pd[(long)(1 * NK + k) * N + c];
+                h = f.Pd[(long)(2 * NK + k) * N + c];
+            } else {
+                m = gm_in[k]; s = gs_in[k]; h = gh_in[k];
+            }
+            double u = f.U[(long)k * N + c];
+            double d = u - m;
+            double e = exp(-d * d / (2.0 * s * s));
+            double gb = dt * zbar[(long)dst[k] * N + c];
+            double dgdu = -2.0 * h * e * d / (s * s);
+            ubar[(long)k * N + c] = gb * dgdu;
+            double dm = gb * (2.0 * h * e * d / (s * s));
+            double ds = gb * (2.0 * h * e * d * d / (s * s * s));
+            double dh = gb * (2.0 * e - 1.0);
+            if (localized) {
+                gPd[(long)(0 * NK + k) * N + c] += dm;
+                gPd[(long)(1 * NK + k) * N + c] += ds;
+                gPd[(long)(2 * NK + k) * N + c] += dh;
+            } else {
+                am += dm; as += ds; ah += dh;
+            }
+        }
+        if (!localized) { gm[k] = am; gs[k] = as; gh[k] = ah; }
+    }
+
+    /* transpose of u_k(x) = sum_d K(d) A(x+d): A_bar(y) += sum_d K(d) ubar(y-d);
+     * and dL/dK(d) = sum_x ubar(x) A(x+d). */
+    for (int ch = 0; ch < C; ++ch) {
+        #pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x) {
+                double acc = 0.0;
+                for (int k = 0; k < NK; ++k) {
+                    if (src[k] != ch) continue;
+                    const double* Ks = K + (long)k * S * S;
+                    const double* Ub = ubar + (long)k * N;
+                    for (int dy = -R; dy <= R; ++dy)
+                        for (int dx = -R; dx <= R; ++dx) {
+                            double kv = Ks[(dy + R) * S + (dx + R)];
+                            if (kv != 0.0) acc += kv * Ub[wrap(y - dy, H) * W + wrap(x - dx, W)];
+                        }
+                }
+                gA[(long)ch * N + y * W + x] += acc;
+            }
+    }
+    for (int k = 0; k < NK; ++k) {
+        const double* As = A + (long)src[k] * N;
+        const double* Ub = ubar + (long)k * N;
+        #pragma omp parallel for schedule(static)
+        for (int t = 0; t < S * S; ++t) {
+            int dy = t / S - R, dx = t % S - R;
+            double acc = 0.0;
+            for (long y = 0; y < H; ++y) {
+                const double* row = As + wrap(y + dy, H) * W;
+                for (long x = 0; x < W; ++x) acc += Ub[y * W + x] * row[wrap(x + dx, W)];
+            }
+            gK[(long)k * S * S + t] = acc;
+        }
+    }
+
+    if (localized) {
+        if (f.genotype_update) {
+            /* mask P' = alpha * Pd, then the diffusion clip and quotient */
+            double* numbar = (double*)calloc((long)NP * N, sizeof(double));
+            if (!numbar) { free(zbar); free(ubar); free(gPd); free_fwd(&f); return -1; }
+            for (long pk = 0; pk < NP; ++pk)
+                for (long c = 0; c < N; ++c) {
+                    long o = pk * N + c;
+                    double pd_bar = f.alpha[c] ? (gP_next[o] + gPd[o]) : 0.0;
+                    double n = f.cnt[o];
+                    if (n > 0.0) {
+                        double q = f.num[o] / n;
+                        if (q >= 0.0 && q <= 1.0) numbar[o] = pd_bar / n;
+                    }
+                }
+            int rd = r_diff;
+            #pragma omp parallel for schedule(static)
+            for (long y = 0; y < H; ++y)
+                for (int pk = 0; pk < NP; ++pk)
+                    for (long x = 0; x < W; ++x) {
+                        double acc = 0.0;
+                        for (int dy = -rd; dy <= rd; ++dy)
+                            for (int dx = -rd; dx <= rd; ++dx) {
+                                if (dy * dy + dx * dx > rd * rd) continue;
+                                acc += numbar[(long)pk * N + wrap(y - dy, H) * W + wrap(x - dx, W)];
+                            }
+                        gP[(long)pk * N + y * W + x] = acc;
+                    }
+            free(numbar);
+        } else {
+            for (long i = 0; i < (long)NP * N; ++i) gP[i] = gP_next[i] + gPd[i];
+        }
+    }
+    if (amb_out) ambiguity(&f, amb_out);
+    free(zbar); free(ubar); free(gPd); free_fwd(&f);
+    return 0;
+}
+
+/*
+ * Gradient of the loss with respect to the shell heights beta_i of one kernel,
+ * through K~ = (sum_i beta_i S_i) / Z, Z = sum_i beta_i |S_i|:
+ *   dL/dbeta_i = (<gK, S_i> - |S_i| <gK, K~>) / Z.
+ * gK is dL/dK~ on the (2R+1)^2 grid; writes B values to gbeta.
+ */
+ORACLE_EXPORT int oracle_beta_grad(int R, int B, const double* beta, const double* gK, double* gbeta)
+{
+    int S = 2 * R + 1;
+    double* Kn = (double*)calloc((long)S * S, sizeof(double));
+    if (!Kn) return -1;
+    double Z = oracle_kernel(R, B, beta, Kn);
+    double gk_dot_k = 0.0;
+    for (int t = 0; t < S * S; ++t) gk_dot_k += gK[t] * Kn[t];
+    for (int i = 0; i < B; ++i) {
+        double dot = 0.0, size = 0.0;
+        for (int dy = -R; dy <= R; ++dy)
+            for (int dx = -R; dx <= R; ++dx) {
+                double sv = oracle_shell_basis(R, B, i, dy, dx);
+                dot += gK[(dy + R) * S + (dx + R)] * sv;
+                size += sv;
+            }
+        gbeta[i] = (Z != 0.0) ? (dot - size * gk_dot_k) / Z : 0.0;
+    }
+    free(Kn);
+    return 0;
+}

@@ -1,0 +1,224 @@
+"""Seeded synthetic worlds for the multi-channel Lenia step.
+
+This module only draws inputs: cell states, gene fields, shell heights and the
+kernel table of the 3-channel / 15-kernel system of Section 2.1 (three
+self-kernels per channel, two cross-kernels per channel pair).  It holds none
+of the method's arithmetic (no kernel construction, convolution, growth or
+update); both the CPU oracle and the HIP library consume its arrays.
+
+The paper names a seed creature whose cell values are not published, so the
+worlds here are random blobs with the paper's shapes (3 channels, 15 kernels,
+radius 12, localized m/s/h genes).  Draw order within one world is fixed:
+
+  1. per kernel: number of shells B = integers(1, 4), then heights random(B);
+  2. gene fields: for p in (m, s, h), for k in 0..14, one smoothed field;
+  3. blobs: for each blob y0 = integers(H), x0 = integers(W),
+     then values random((3, 24, 24)), stamped with wrap-around, later blobs
+     overwriting earlier ones;
+  4. (large world only) per-blob genes: for each blob 15 m, 15 s, 15 h,
+     stamped into the 48x48 square centred on the blob;
+  5. (rollout workload only) the loss target random((3, H, W)).
+
+A smoothed field is i.i.d. N(0,1) noise, blurred on the torus by a Gaussian of
+standard deviation 16 cells (side/8 on tori smaller than 128; FP64, FFT), divided by its empirical standard
+deviation, mapped through the normal CDF to a uniform marginal and affinely to
+[lo, hi], then rounded to float32.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Tuple
+
+import numpy as np
+import scipy.fft as sfft
+from scipy.special import ndtr
+
+SEED_BASE = 2304056390
+
+# Kernel table: k = 0..8 self kernels (source = target = k // 3); k = 9..14 one
+# cross kernel per ordered channel pair.
+KERNEL_SRC_3CH = (0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 2)
+KERNEL_DST_3CH = (0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 2, 0, 2, 0, 1)
+
+GENE_RANGES = {"m": (0.1, 0.4), "s": (0.01, 0.1), "h": (0.0, 1.0)}
+BLOB = 24
+C4_SIDES = (128, 192, 256, 384, 512, 768, 1024)
+
+
+@dataclasses.dataclass
+class World:
+    """One Lenia world: descriptor fields plus the initial state arrays."""
+    H: int
+    W: int
+    n_channels: int
+    n_kernels: int
+    src: Tuple[int, ...]
+    dst: Tuple[int, ...]
+    R: int
+    n_shells: np.ndarray          # int32 [k]
+    beta: np.ndarray              # float64 [k, 3]; entries >= n_shells are 0
+    dt: float
+    localized: int
+    genotype_update: int
+    m: Optional[np.ndarray]       # float64 [k], global mode only
+    s: Optional[np.ndarray]
+    h: Optional[np.ndarray]
+    eps: float
+    r_diff: int
+    A: np.ndarray                 # float32 [c, H, W]
+    P: Optional[np.ndarray]       # float32 [3, k, H, W] (m, s, h planes)
+    target: Optional[np.ndarray] = None
+    name: str = ""
+
+    @property
+    def cells(self) -> int:
+        return self.H * self.W
+
+
+def smooth_uniform_field(rng: np.random.Generator, H: int, W: int,
+                         lo: float, hi: float, sigma: float = 16.0) -> np.ndarray:
+    z = rng.standard_normal((H, W))
+    fy = np.fft.fftfreq(H)[:, None]
+    fx = np.fft.rfftfreq(W)[None, :]
+    g = np.exp(-2.0 * np.pi ** 2 * sigma ** 2 * (fy ** 2 + fx ** 2))
+    y = sfft.irfft2(sfft.rfft2(z, workers=-1) * g, s=(H, W), workers=-1)
+    sd = y.std()
+    if sd > 0:
+        y = y / sd
+    u = ndtr(y)
+    return (lo + (hi - lo) * u).astype(np.float32)
+
+
+def _draw_shells(rng: np.random.Generator, n_kernels: int):
+    n_shells = np.zeros(n_kernels, np.int32)
+    beta = np.zeros((n_kernels, 3), np.float64)
+    for k in range(n_kernels):
+        b = int(rng.integers(1, 4))
+        n_shells[k] = b
+        # heights are rounded to float32 so that every consumer sees the same value
+        beta[k, :b] = rng.random(b).astype(np.float32)
+    return n_shells, beta
+
+
+def _stamp(dst: np.ndarray, vals: np.ndarray, y0: int, x0: int) -> None:
+    """dst[..., (y0+i) % H, (x0+j) % W] = vals[..., i, j] (later writes win)."""
+    H, W = dst.shape[-2:]
+    h, w = vals.shape[-2:]
+    ys = (y0 + np.arange(h)) % H
+    xs = (x0 + np.arange(w)) % W
+    # sequential row assignment so that self-overlap on tiny tori keeps the last write
+    for i in range(h):
+        dst[..., ys[i], xs] = vals[..., i, :]
+
+
+def default_sigma(H: int, W: int) -> float:
+    """16 cells, reduced to side/8 on small test tori where a 16-cell blur would
+    leave an almost constant field (worlds of side >= 128 always get 16)."""
+    return min(16.0, min(H, W) / 8.0)
+
+
+def localized_world(rng: np.random.Generator, H: int, W: int, n_blobs: int,
+                    per_blob_genes: bool = False, with_target: bool = False,
+                    R: int = 12, dt: float = 0.2, genotype_update: int = 1,
+                    name: str = "", sigma: Optional[float] = None) -> World:
+    """3-channel, 15-kernel world with smoothed m/s/h fields and uniform blobs."""
+    sig = default_sigma(H, W) if sigma is None else sigma
+    nk = 15
+    n_shells, beta = _draw_shells(rng, nk)
+    P = np.empty((3, nk, H, W), np.float32)
+    for pi, p in enumerate(("m", "s", "h")):
+        lo, hi = GENE_RANGES[p]
+        for k in range(nk):
+            P[pi, k] = smooth_uniform_field(rng, H, W, lo, hi, sig)
+    A = np.zeros((3, H, W), np.float32)
+    corners = []
+    for _ in range(n_blobs):
+        y0 = int(rng.integers(H))
+        x0 = int(rng.integers(W))
+        vals = rng.random((3, BLOB, BLOB)).astype(np.float32)
+        _stamp(A, vals, y0, x0)
+        corners.append((y0, x0))
+    if per_blob_genes:
+        side = 2 * BLOB
+        for (y0, x0) in corners:
+            genes = np.empty((3, nk), np.float32)
+            for pi, p in enumerate(("m", "s", "h")):
+                lo, hi = GENE_RANGES[p]
+                genes[pi] = (lo + (hi - lo) * rng.random(nk)).astype(np.float32)
+            block = np.broadcast_to(genes[:, :, None, None], (3, nk, side, side))
+            _stamp(P, block, y0 + BLOB // 2 - side // 2, x0 + BLOB // 2 - side // 2)
+    target = rng.random((3, H, W)).astype(np.float32) if with_target else None
+    return World(H=H, W=W, n_channels=3, n_kernels=nk, src=KERNEL_SRC_3CH,
+                 dst=KERNEL_DST_3CH, R=R, n_shells=n_shells, beta=beta, dt=dt,
+                 localized=1, genotype_update=genotype_update, m=None, s=None,
+                 h=None, eps=0.01, r_diff=1, A=A, P=P, target=target, name=name)
+
+
+def orbium_like_world(seed: Optional[int] = None, H: int = 64, W: int = 64,
+                      patch: int = 20, R: int = 13) -> World:
+    """Single-channel, single-kernel world with global genes (m=0.15, s=0.015,
+    dt=0.1, one shell of height 1) and a centred uniform patch."""
+    rng = np.random.default_rng(SEED_BASE + 1 if seed is None else seed)
+    A = np.zeros((1, H, W), np.float32)
+    y0 = (H - patch) // 2
+    x0 = (W - patch) // 2
+    A[0, y0:y0 + patch, x0:x0 + patch] = rng.random((patch, patch)).astype(np.float32)
+    return World(H=H, W=W, n_channels=1, n_kernels=1, src=(0,), dst=(0,), R=R,
+                 n_shells=np.array([1], np.int32),
+                 beta=np.array([[1.0, 0.0, 0.0]]), dt=0.1, localized=0,
+                 genotype_update=0, m=np.array([0.15]), s=np.array([0.015]),
+                 h=np.array([1.0]), eps=0.01, r_diff=1, A=A, P=None,
+                 name=f"global-1ch-{H}x{W}")
+
+
+# ---- the five standard workloads -------------------------------------------
+
+def config1() -> World:
+    """64x64 torus, 1 channel, 1 kernel (R=13), global genes, 100 steps."""
+    return orbium_like_world()
+
+
+def config2() -> World:
+    """512x512 torus, 3 channels, 15 kernels, localized genes, 40 blobs."""
+    rng = np.random.default_rng(SEED_BASE + 2)
+    return localized_world(rng, 512, 512, 40, name="lenia-3ch15k-512")
+
+
+def config3(H: int = 4096, W: int = 4096, n_blobs: int = 2000) -> World:
+    """4096x4096 torus, 2000 blobs each with its own genotype."""
+    rng = np.random.default_rng(SEED_BASE + 3)
+    return localized_world(rng, H, W, n_blobs, per_blob_genes=True,
+                           name=f"lenia-3ch15k-{H}")
+
+
+def blobs_for_side(side: int) -> int:
+    return max(1, int(round(40 * side * side / (512 * 512))))
+
+
+def config4(n_worlds: int = 256) -> List[World]:
+    """Independent worlds of uneven square sides, each seeded separately."""
+    seqs = np.random.SeedSequence(SEED_BASE + 4).spawn(n_worlds)
+    worlds = []
+    for i, sq in enumerate(seqs):
+        rng = np.random.default_rng(sq)
+        side = C4_SIDES[int(rng.integers(len(C4_SIDES)))]
+        worlds.append(localized_world(rng, side, side, blobs_for_side(side),
+                                      name=f"batch{i}-{side}"))
+    return worlds
+
+
+def config5() -> World:
+    """256x256 torus with a random loss target, for differentiable rollouts."""
+    rng = np.random.default_rng(SEED_BASE + 5)
+    return localized_world(rng, 256, 256, blobs_for_side(256), with_target=True,
+                           name="lenia-3ch15k-256-rollout")
+
+
+def test_world(H: int, W: int, seed: int, n_blobs: Optional[int] = None,
+               R: int = 12, genotype_update: int = 1, dt: float = 0.2) -> World:
+    """A small localized world for parity tests (blob density of the 512 case
+    unless given)."""
+    rng = np.random.default_rng(seed)
+    nb = blobs_for_side(int(np.sqrt(H * W))) if n_blobs is None else n_blobs
+    return localized_world(rng, H, W, nb, R=R, genotype_update=genotype_update,
+                           dt=dt, name=f"test-{H}x{W}-s{seed}")
