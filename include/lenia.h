@@ -1,0 +1,182 @@
+/*
+ * lenia.h - C ABI of the MI355X (gfx950) multi-channel Lenia library.
+ *
+ * One step of 2-D, multi-channel Lenia on a torus with per-cell ("localized")
+ * growth genes, following Chan, "Towards Large-Scale Simulations of
+ * Open-Ended Evolution in Continuous Cellular Automata" (GECCO 2023):
+ *   Section 2.1  3 channels, 15 kernels (3 self-kernels per channel, 2 cross-
+ *                kernels per channel pair), normalized kernels K~ = K/sum(K),
+ *                clipped update A <- clip01(A + sum_k G_k(K~_k * A)).
+ *   Section 2.2  genes in a tensor P[p][k][y][x]; alpha mask = all potentials
+ *                above the cutoff eps AND all genes above eps; P <- P * alpha.
+ *   Section 2.3  gene diffusion: P <- clip01((P * Kdiff) / (count of
+ *                above-eps neighbours within Kdiff)), Kdiff a disk.
+ *   Section 2.4  growth of kernel k at a cell uses that cell's m, s, h genes.
+ *   Algorithm 2  order per step: diffuse -> convolve -> alpha -> mask -> grow.
+ * Readings taken where the paper is silent (see the design notes):
+ *   kernel of kernel k: K(d) = beta_{k,i} * exp(4 - 1/(r(1-r))) for |d| < R,
+ *     i = floor(B_k |d|/R), r = B_k |d|/R - i (ring shells, B_k in 1..3);
+ *   growth G(u; m,s,h) = h * (2 exp(-(u-m)^2/(2 s^2)) - 1);
+ *   update A' = clip01(A + dt * sum_{k: dst(k)=c} g_k), summed in ascending k;
+ *   the alpha mask thresholds the potentials u_k = K~_k * A (strict > eps);
+ *   the diffusion disk is |d| <= r_diff; a cell with no above-eps neighbour
+ *   gets gene 0; only m, s, h are localized (kernel heights are global).
+ *
+ * Layouts (all row-major FP32, device memory, 4-byte aligned):
+ *   A  float[C][H][W]             cell states
+ *   P  float[3][NK][H][W]         gene planes m (k = 0..NK-1), then s, then h
+ * Ownership: the caller owns every state, gene, gradient and `saved` buffer;
+ * a plan owns its workspaces and tables and frees them in lenia_plan_destroy.
+ * Streams: every call only enqueues work on `stream` (a hipStream_t, NULL =
+ * the null stream) and returns without synchronizing; device faults surface at
+ * the caller's next synchronization.  A plan must not be used from two host
+ * threads at once; distinct plans are independent.
+ * Errors: arguments are validated before anything is enqueued; on error no
+ * work is enqueued and caller buffers are untouched.  No C++ exception crosses
+ * this ABI; lenia_last_error() gives a thread-local detail string.
+ */
+#ifndef LENIA_H
+#define LENIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LENIA_API __attribute__((visibility("default")))
+
+typedef enum {
+    LENIA_OK = 0,
+    LENIA_ERR_INVALID_ARG = 1,   /* malformed descriptor or call arguments   */
+    LENIA_ERR_UNSUPPORTED = 2,   /* valid, but outside what the kernels build */
+    LENIA_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                  */
+    LENIA_ERR_HIP = 4,           /* a HIP runtime call or launch failed       */
+    LENIA_ERR_STATE = 5          /* call not valid for this plan              */
+} lenia_status;
+
+/* How the potentials u_k = K~_k * A are computed.  Every form computes the
+ * same circular convolution; they differ in arithmetic and speed. */
+typedef enum {
+    LENIA_CONV_AUTO = 0,             /* library choice (currently DIRECT_F32)       */
+    LENIA_CONV_DIRECT_F32 = 1,       /* direct torus sum in FP32, taps folded by the
+                                        kernel's 8-fold lattice symmetry              */
+    LENIA_CONV_DFT_SPLIT_BF16 = 2,   /* tile-local DFT as matrix products on MFMA,
+                                        bf16 hi+lo operands, FP32 accumulation       */
+    LENIA_CONV_DFT_SPLIT_F16 = 3     /* as above with fp16 hi+lo operands            */
+} lenia_conv;
+
+#define LENIA_MAX_CHANNELS 3
+#define LENIA_MAX_KERNELS 15
+#define LENIA_MAX_SHELLS 3
+
+/* Descriptor of one world.  All pointers are host pointers read only during
+ * lenia_plan / lenia_plan_batched / lenia_desc_validate. */
+typedef struct {
+    int32_t H, W;               /* torus rows, columns (>= 1)                    */
+    int32_t n_channels;         /* C: 1 or 3                                     */
+    int32_t n_kernels;          /* NK: 1 (with C = 1) or 15 (with C = 3)         */
+    const int32_t* src;         /* [NK] source channel of each kernel            */
+    const int32_t* dst;         /* [NK] target channel of each kernel            */
+    int32_t R;                  /* kernel radius in cells (12 or 13)             */
+    const int32_t* n_shells;    /* [NK] B_k in 1..3                              */
+    const double* beta;         /* [NK][3] shell heights; the first B_k are used */
+    double dt;                  /* time step, > 0                                */
+    int32_t localized;          /* 0: global genes m,s,h below; 1: genes in P    */
+    int32_t genotype_update;    /* 1: diffuse + alpha-mask P each step (needs
+                                   localized); 0: genes are read-only            */
+    const double* m;            /* [NK] global genes, used iff localized == 0    */
+    const double* s;            /*      (s > 0)                                  */
+    const double* h;
+    double eps;                 /* mask cutoff (0.01), in [0, 1)                 */
+    int32_t r_diff;             /* diffusion disk radius (1)                     */
+    int32_t conv;               /* lenia_conv                                    */
+    int32_t tile_y, tile_x;     /* output tile of the fused step kernel; 0,0 =
+                                   the autotuned / default choice                */
+    uint32_t flags;             /* LENIA_FLAG_*                                  */
+} lenia_desc;
+
+#define LENIA_FLAG_AUTOTUNE 1u  /* time the tile candidates at plan time and
+                                   cache the winner per (H, W, R, C, mode)       */
+
+typedef struct lenia_plan_* lenia_plan_t;
+
+/* Information about a plan (what the library chose). */
+typedef struct {
+    int32_t conv;               /* lenia_conv actually used                      */
+    int32_t tile_y, tile_x;     /* tile of the fused step kernel                 */
+    int32_t n_worlds;           /* 1, or the batch size of a batched plan        */
+    int64_t cells;              /* sum of H*W over worlds                        */
+    size_t workspace_bytes;     /* device memory owned by the plan               */
+    size_t saved_bytes;         /* lenia_saved_bytes()                           */
+} lenia_plan_info;
+
+/* Checks a descriptor on the host only (no device call): LENIA_OK,
+ * LENIA_ERR_INVALID_ARG (malformed) or LENIA_ERR_UNSUPPORTED. */
+LENIA_API lenia_status lenia_desc_validate(const lenia_desc* d);
+
+/* The normalized kernel K~_k (Section 2.1) that a plan for `d` uses, in FP64
+ * on the (2R+1)x(2R+1) offset grid, index [(dy+R)*(2R+1) + (dx+R)], computed
+ * on the host before rounding to FP32.  `out` holds (2R+1)^2 doubles. */
+LENIA_API lenia_status lenia_kernel_taps(const lenia_desc* d, int32_t k, double* out);
+
+/* Builds a plan for one world: kernel tables (FP64 on the host, rounded to
+ * FP32), device workspaces, tile choice.  Uploads on `stream`. */
+LENIA_API lenia_status lenia_plan(const lenia_desc* d, void* stream, lenia_plan_t* out);
+
+/* Builds a plan for n_worlds independent worlds (sizes may differ; each has
+ * its own kernels and genes), stepped together by lenia_step_batched. */
+LENIA_API lenia_status lenia_plan_batched(const lenia_desc* descs, int32_t n_worlds, void* stream,
+                                lenia_plan_t* out);
+
+/*
+ * Advances one world by n_steps >= 0 steps (Algorithm 2 without its random
+ * operators): from (A_in, P_in) to (A_out, P_out).  A_out may equal A_in and
+ * P_out may equal P_in (in place); otherwise the buffers must not overlap.
+ * P_in / P_out are ignored (may be NULL) when localized == 0; P_out is not
+ * written when genotype_update == 0 (genes read-only).
+ * saved: NULL, or (only with n_steps == 1) a device buffer of
+ * lenia_saved_bytes() bytes that receives the step's potentials u_k
+ * (float[NK][H][W]) followed by the alpha mask (uint8[H][W]), for
+ * lenia_backward.
+ */
+LENIA_API lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in,
+                        float* A_out, float* P_out, int32_t n_steps, void* saved,
+                        void* stream);
+
+/* Advances every world of a batched plan by n_steps, in place: A[i], P[i] are
+ * device pointers of world i (host arrays of n_worlds pointers).  The steps
+ * run as one persistent launch per step over a (world, tile) work list,
+ * captured once into a HIP graph per pointer set and replayed. */
+LENIA_API lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P,
+                                int32_t n_steps, void* stream);
+
+/* Bytes of the `saved` buffer of lenia_step / lenia_backward. */
+LENIA_API size_t lenia_saved_bytes(lenia_plan_t p);
+
+/*
+ * Vector-Jacobian product of one step (A_t, P_t) -> (A_{t+1}, P_{t+1}) of a
+ * single-world plan with localized == 1.  `saved` is what lenia_step(...,
+ * n_steps = 1, saved) wrote for this (A_t, P_t).  Given gA_next, gP_next
+ * (cotangents of A_{t+1}, P_{t+1}; gP_next may be NULL = zero), writes
+ *   gA_t  float[C][H][W]        (overwritten)
+ *   gP_t  float[3][NK][H][W]    (overwritten)
+ * and ADDS the shell-height gradient into gbeta float[NK][3] (entries
+ * >= B_k untouched).  The alpha mask and diffusion counts are piecewise
+ * constant and carry no gradient; clips use the inclusive subgradient.
+ * gA_t / gP_t must not alias any input.
+ */
+LENIA_API lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const float* P_t,
+                            const void* saved, const float* gA_next, const float* gP_next,
+                            float* gA_t, float* gP_t, float* gbeta, void* stream);
+
+LENIA_API lenia_status lenia_plan_get_info(lenia_plan_t p, lenia_plan_info* info);
+LENIA_API lenia_status lenia_plan_destroy(lenia_plan_t p);
+LENIA_API const char* lenia_status_str(lenia_status s);
+LENIA_API const char* lenia_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENIA_H */

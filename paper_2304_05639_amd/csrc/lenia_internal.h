@@ -1,0 +1,123 @@
+// Internal declarations shared by the host plan code and the HIP kernels of
+// liblenia.so.  Not part of the public ABI (include/lenia.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lenia {
+
+// ---------------------------------------------------------------------------
+// Kernel-offset orbits.  A ring-shell kernel depends on |d| only, so it is
+// invariant under the 8 symmetries of the square lattice.  Offsets with
+// 0 < |d| < R fall into orbits represented by (a, b), 0 <= b <= a:
+//   b == 0 : (+-a, 0), (0, +-a)          4 offsets
+//   b == a : (+-a, +-a)                  4 offsets
+//   else   : (+-a, +-b), (+-b, +-a)      8 offsets
+// The centre (0, 0) has weight 0 (the shell core vanishes at r = 0) and is
+// not an orbit.  The convolution sums the cells of an orbit first and
+// multiplies once per kernel.
+// ---------------------------------------------------------------------------
+template <int R>
+struct Orbits {
+    static constexpr int count()
+    {
+        int n = 0;
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a * a + b * b > 0 && a * a + b * b < R * R) ++n;
+        return n;
+    }
+    static constexpr int N = count();
+    struct Tab {
+        int a[N];
+        int b[N];
+    };
+    static constexpr Tab make()
+    {
+        Tab t{};
+        int n = 0;
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a * a + b * b > 0 && a * a + b * b < R * R) {
+                    t.a[n] = a;
+                    t.b[n] = b;
+                    ++n;
+                }
+        return t;
+    }
+    static constexpr Tab tab = make();
+};
+
+inline int orbit_count(int R)
+{
+    int n = 0;
+    for (int a = 0; a < R; ++a)
+        for (int b = 0; b <= a; ++b)
+            if (a * a + b * b > 0 && a * a + b * b < R * R) ++n;
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel tables compiled into the kernels: for each source channel the kernels
+// reading it ("slots"), and each kernel's target channel.
+// ---------------------------------------------------------------------------
+struct Table1x1 {
+    static constexpr int C = 1, NK = 1, KPS = 1;
+    static constexpr int kidx[1][1] = {{0}};
+    static constexpr int src[1] = {0};
+    static constexpr int dst[1] = {0};
+};
+
+// 3 channels, 15 kernels: k = 0..8 self (channel k/3), k = 9..14 cross
+// (0->1, 0->2, 1->0, 1->2, 2->0, 2->1).
+struct Table3x15 {
+    static constexpr int C = 3, NK = 15, KPS = 5;
+    static constexpr int kidx[3][5] = {{0, 1, 2, 9, 10}, {3, 4, 5, 11, 12}, {6, 7, 8, 13, 14}};
+    static constexpr int src[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 2};
+    static constexpr int dst[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 2, 0, 2, 0, 1};
+};
+
+enum TableId { TABLE_1x1 = 0, TABLE_3x15 = 1 };
+
+enum Mode { MODE_GLOBAL = 0, MODE_LOCAL_READONLY = 1, MODE_LOCAL_UPDATE = 2 };
+
+constexpr int kMaxK = 16;
+
+// One world as seen by the step kernels.
+struct WorldArgs {
+    const float* A;        // [C][H][W]
+    const float* P;        // [3][NK][H][W] or null
+    float* A_out;
+    float* P_out;          // null when genes are read-only
+    float* U_save;         // [NK][H][W] or null
+    uint8_t* alpha_save;   // [H][W] or null
+    const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
+    int H, W;
+    int tiles_x, n_tiles;  // tile grid of this world
+    float dt;
+    float eps;             // the largest float <= the descriptor's eps, so that
+                           // (float x > eps) == ((double)x > eps_double)
+    float gm[kMaxK], gs[kMaxK], gh[kMaxK];   // global genes (MODE_GLOBAL)
+};
+
+// Work list of a batched step: item i is tile items[i].y of world items[i].x.
+struct BatchList {
+    const WorldArgs* worlds;
+    const int2* items;
+    int n_items;
+};
+
+// Launchers (defined in lenia_step.hip).  Return hipSuccess or the launch error.
+typedef hipError_t (*step_launch_fn)(const WorldArgs& w, int mode, hipStream_t s);
+typedef hipError_t (*batch_launch_fn)(const BatchList& b, int mode, int grid, hipStream_t s);
+
+step_launch_fn find_step_launcher(int table, int R, int ty, int tx);
+batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx);
+// candidate tiles compiled for (table, R); returns count, fills up to max pairs
+int step_tile_candidates(int table, int R, int* ty, int* tx, int max);
+hipError_t launch_fill_synthetic(float* A, size_t nA, float* P, size_t plane, int nk,
+                                 hipStream_t s);
+
+}  // namespace lenia

@@ -1,0 +1,72 @@
+// Plan object behind the opaque lenia_plan_t handle (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "lenia.h"
+#include "lenia_internal.h"
+
+namespace lenia {
+
+lenia_status set_error(lenia_status s, const std::string& msg);
+lenia_status hip_fail(hipError_t e, const char* what);
+lenia_status validate(const lenia_desc* d);
+int table_of(const lenia_desc* d);
+int mode_of(const lenia_desc* d);
+float eps_below(double eps);
+double raw_kernel_tap(int R, int B, const double* beta, int dy, int dx);
+double raw_kernel_sum(int R, int B, const double* beta);
+void orbit_list(int R, std::vector<int>& a, std::vector<int>& b);
+int orbit_size(int a, int b);
+bool conv_form_supported(int conv, int table, int R);
+
+// One world of a plan, with its descriptor arrays copied.
+struct WorldPlan {
+    int H = 0, W = 0, C = 0, NK = 0, R = 0, mode = 0;
+    double dt = 0, eps = 0;
+    std::vector<int> n_shells;
+    std::vector<double> beta;      // [NK][3]
+    std::vector<double> gm, gs, gh;
+    int n_orbits = 0;
+    float* d_w = nullptr;          // [NK][n_orbits] orbit weights of K~_k
+    float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
+    float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
+    float* ws_P = nullptr;         // [3][NK][H][W] (gene update only)
+    size_t cells() const { return (size_t)H * W; }
+    size_t a_elems() const { return (size_t)C * H * W; }
+    size_t p_elems() const { return (size_t)3 * NK * H * W; }
+    WorldArgs args_template() const;
+};
+
+struct BackwardWs {
+    float* ubar = nullptr;         // [NK][H][W]
+    float* numbar = nullptr;       // [3NK][H][W]
+    float* part = nullptr;         // [n_tiles][NK][3] beta-gradient partials
+    int n_part = 0;
+};
+
+}  // namespace lenia
+
+struct lenia_plan_ {
+    std::vector<lenia::WorldPlan> worlds;
+    bool batched = false;
+    int table = 0, mode = 0, R = 0, conv = LENIA_CONV_DIRECT_F32;
+    int tile_y = 0, tile_x = 0;
+    lenia::step_launch_fn step_fn = nullptr;
+    lenia::batch_launch_fn batch_fn = nullptr;
+    size_t ws_bytes = 0;
+    int device = 0;
+    // batched execution
+    lenia::WorldArgs* d_tables[2] = {nullptr, nullptr};   // phase 0: X -> ws, 1: ws -> X
+    int2* d_items = nullptr;
+    int n_items = 0, grid = 0;
+    std::vector<float*> graph_A, graph_P;                 // pointer set of the graph
+    hipGraphExec_t graph = nullptr;
+    hipStream_t graph_stream = nullptr;
+    // adjoint
+    lenia::BackwardWs bw;
+    std::vector<void*> allocations;
+};

@@ -1,0 +1,136 @@
+"""Host-only checks of the C ABI (no device call): the library loads, exports
+every entry point the header declares, validates descriptors with the right
+status codes, and builds the same FP64 kernels as the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_05639_amd import inputs
+from paper_2304_05639_amd import lenia as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"LENIA_API\s+[\w\s\*]+?\b(lenia_\w+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_symbols()
+    assert len(names) >= 12
+    lib = L.lib()
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(L.API) == names
+
+
+def _ok(w, **kw):
+    return L.validate(w, **kw)
+
+
+def test_standard_workloads_validate():
+    for w in (inputs.config1(), inputs.test_world(64, 64, seed=1)):
+        assert _ok(w) == L.OK, L.last_error()
+
+
+def _mut(w, **changes):
+    import copy
+    w2 = copy.copy(w)
+    for k, v in changes.items():
+        setattr(w2, k, v)
+    return w2
+
+
+@pytest.mark.parametrize("changes", [
+    dict(H=0), dict(W=-3), dict(dt=0.0), dict(dt=float("nan")), dict(eps=1.5),
+    dict(eps=-0.1), dict(localized=2), dict(genotype_update=3),
+    dict(n_shells=np.array([0] * 15, np.int32)), dict(n_shells=np.array([4] * 15, np.int32)),
+    dict(beta=np.zeros((15, 3))), dict(beta=np.full((15, 3), -1.0)),
+    dict(src=tuple([5] * 15)), dict(R=0), dict(r_diff=-1),
+])
+def test_invalid_descriptors(changes):
+    w = _mut(inputs.test_world(32, 32, seed=2, n_blobs=1), **changes)
+    assert _ok(w) == L.ERR_INVALID_ARG, changes
+
+
+def test_global_mode_needs_positive_s():
+    w = inputs.config1()
+    w2 = _mut(w, s=np.array([0.0]))
+    assert _ok(w2) == L.ERR_INVALID_ARG
+    w3 = _mut(w, genotype_update=1)       # gene update without localized genes
+    assert _ok(w3) == L.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("changes", [
+    dict(R=7), dict(r_diff=2),
+    dict(src=(0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 1)),
+])
+def test_unsupported_descriptors(changes):
+    w = _mut(inputs.test_world(32, 32, seed=2, n_blobs=1), **changes)
+    assert _ok(w) == L.ERR_UNSUPPORTED, changes
+    assert len(L.last_error()) > 0
+
+
+def test_unknown_tile_and_flags():
+    w = inputs.test_world(32, 32, seed=2, n_blobs=1)
+    assert _ok(w, tile=(24, 24)) == L.ERR_UNSUPPORTED
+    assert _ok(w, tile=(32, 64)) == L.OK
+    b = L.DescBuilder(w)
+    b.desc.flags = 0x80
+    import ctypes
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.ERR_INVALID_ARG
+    b.desc.flags = 0
+    b.desc.tile_y = 32
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.ERR_INVALID_ARG
+
+
+def test_status_strings():
+    lib = L.lib()
+    for code, name in [(0, b"LENIA_OK"), (1, b"LENIA_ERR_INVALID_ARG"), (4, b"LENIA_ERR_HIP")]:
+        assert lib.lenia_status_str(code) == name
+
+
+def test_null_descriptor_rejected():
+    assert L.lib().lenia_desc_validate(None) == L.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_plan_kernels_match_oracle(oracle, seed):
+    w = inputs.test_world(32, 32, seed=seed, n_blobs=1)
+    for k in range(15):
+        K_lib = L.kernel_taps(w, k)
+        K_or, _ = oracle.kernel(w.R, int(w.n_shells[k]), w.beta[k])
+        assert np.abs(K_lib - K_or).max() <= 1e-17
+    w1 = inputs.config1()
+    K_lib = L.kernel_taps(w1, 0)
+    K_or, _ = oracle.kernel(13, 1, [1.0])
+    assert np.abs(K_lib - K_or).max() <= 1e-17
+
+
+def test_package_import_does_not_load_library():
+    import subprocess
+    import sys
+    code = ("import paper_2304_05639_amd as p, paper_2304_05639_amd.lenia as L, sys;"
+            "sys.exit(0 if not L.library_loaded() else 1)")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT)
+    assert r.returncode == 0
+
+
+def test_missing_library_raises(tmp_path, monkeypatch):
+    import importlib
+    import paper_2304_05639_amd.lenia as mod
+    m2 = importlib.reload(mod)
+    try:
+        monkeypatch.setattr(m2, "LIB_PATH", str(tmp_path / "nope.so"))
+        m2._lib = None
+        with pytest.raises(ImportError):
+            m2.lib()
+    finally:
+        importlib.reload(mod)

@@ -1,0 +1,201 @@
+"""GPU parity of the fused step (HIP path through the C ABI) against the FP64
+oracle: per-step teacher forcing on identical FP32 inputs, max-abs <= 1e-5 on
+A' and P' over cells whose alpha decision is not within 1e-5 of the cutoff."""
+import numpy as np
+import pytest
+
+from paper_2304_05639_amd import inputs
+
+from gpu_helpers import TOL_STATE, compare_step, dev, gpu_step, host, window
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_05639_amd import lenia
+    lenia.lib()
+    return lenia
+
+
+def _parity(L, oracle, w, **plan_kw):
+    d = oracle.Desc.from_world(w)
+    plan = L.Plan(w, **plan_kw)
+    A1, P1 = gpu_step(plan, w.A, w.P)
+    r = oracle.step(d, w.A, w.P)
+    return compare_step(r, A1, P1)
+
+
+def test_global_single_channel_rollout_teacher_forced(L, oracle):
+    """64x64, one kernel R=13, global genes: every one of 100 steps."""
+    w = inputs.config1()
+    d = oracle.Desc.from_world(w)
+    plan = L.Plan(w)
+    A = w.A.astype(np.float32)
+    worst = 0.0
+    for t in range(100):
+        A1, _ = gpu_step(plan, A, None)
+        r = oracle.step(d, A)
+        errA, _, _ = compare_step(r, A1, None)
+        worst = max(worst, errA)
+        A = r["A"].astype(np.float32)       # teacher forcing from the oracle state
+    print(f"global 64x64: worst per-step max-abs {worst:.3e} over 100 steps")
+
+
+@pytest.mark.parametrize("H,W,seed", [(16, 16, 101), (40, 56, 102), (100, 150, 103),
+                                      (64, 64, 104), (3, 5, 105), (1, 1, 106), (129, 67, 107),
+                                      (24, 200, 108)])
+def test_localized_parity_sizes(L, oracle, H, W, seed):
+    """Several tiles, ragged tails, tori smaller than the kernel (multi-wrap)."""
+    nb = max(1, H * W // 600)
+    w = inputs.test_world(H, W, seed=seed, n_blobs=nb)
+    errA, errP, n_amb = _parity(L, oracle, w)
+    print(f"{H}x{W}: errA {errA:.2e} errP {errP:.2e} ambiguous {n_amb}")
+
+
+def test_localized_readonly_genes(L, oracle):
+    w = inputs.test_world(70, 90, seed=111, n_blobs=6, genotype_update=0)
+    _parity(L, oracle, w)
+
+
+def test_r13_three_channels(L, oracle):
+    w = inputs.test_world(48, 80, seed=112, n_blobs=4, R=13)
+    _parity(L, oracle, w)
+
+
+def test_c2_teacher_forced_steps(L, oracle):
+    """512x512, 15 kernels, localized genes: steps 0, 1, 2 and 6 teacher-forced."""
+    w = inputs.config2()
+    d = oracle.Desc.from_world(w)
+    plan = L.Plan(w)
+    A, P = w.A.astype(np.float64), w.P.astype(np.float64)
+    for t in range(7):
+        A32, P32 = A.astype(np.float32), P.astype(np.float32)
+        r = oracle.step(d, A32, P32)
+        if t in (0, 1, 2, 6):
+            A1, P1 = gpu_step(plan, A32, P32)
+            errA, errP, n_amb = compare_step(r, A1, P1)
+            print(f"512^2 step {t}: errA {errA:.2e} errP {errP:.2e} ambiguous {n_amb}")
+        A, P = r["A"], r["P"]
+
+
+def test_zero_world_stays_zero(L):
+    w = inputs.test_world(64, 64, seed=113, n_blobs=0)
+    plan = L.Plan(w)
+    A1, P1 = gpu_step(plan, np.zeros_like(w.A), w.P, n_steps=3)
+    assert (A1 == 0).all() and (P1 == 0).all()
+    w1 = inputs.config1()
+    plan1 = L.Plan(w1)
+    A1, _ = gpu_step(plan1, np.zeros_like(w1.A), None, n_steps=100)
+    assert (A1 == 0).all()
+
+
+def test_tiles_agree_bitwise(L):
+    """Each cell's arithmetic does not depend on its tile: all tile shapes give
+    identical bits."""
+    w = inputs.test_world(160, 192, seed=114, n_blobs=8)
+    outs = []
+    for tile in [(16, 64), (32, 64), (32, 32), (64, 64)]:
+        plan = L.Plan(w, tile=tile)
+        assert (plan.info().tile_y, plan.info().tile_x) == tile
+        outs.append(gpu_step(plan, w.A, w.P))
+    for A1, P1 in outs[1:]:
+        assert np.array_equal(A1, outs[0][0]) and np.array_equal(P1, outs[0][1])
+
+
+def test_translation_bitwise(L):
+    w = inputs.test_world(96, 128, seed=115, n_blobs=5)
+    plan = L.Plan(w)
+    A0, P0 = gpu_step(plan, w.A, w.P)
+    sy, sx = 37, -45
+    A1, P1 = gpu_step(plan, np.roll(w.A, (sy, sx), (1, 2)), np.roll(w.P, (sy, sx), (2, 3)))
+    assert np.array_equal(A1, np.roll(A0, (sy, sx), (1, 2)))
+    assert np.array_equal(P1, np.roll(P0, (sy, sx), (2, 3)))
+
+
+def test_deterministic(L):
+    w = inputs.test_world(128, 128, seed=116, n_blobs=6)
+    plan = L.Plan(w)
+    a = gpu_step(plan, w.A, w.P, n_steps=5)
+    b = gpu_step(plan, w.A, w.P, n_steps=5)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_multistep_schedules_agree(L):
+    """n steps in one call (out of place, in place, odd/even) == n single calls."""
+    import torch
+    w = inputs.test_world(96, 96, seed=117, n_blobs=5)
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    ref = [(A.clone(), P.clone())]
+    for _ in range(5):
+        a, p = plan.step(ref[-1][0], ref[-1][1])
+        ref.append((a, p))
+    for n in (0, 1, 2, 3, 4, 5):
+        a, p = plan.step(A, P, n_steps=n)                    # out of place
+        torch.cuda.synchronize()
+        assert torch.equal(a, ref[n][0]) and torch.equal(p, ref[n][1]), n
+        a2, p2 = A.clone(), P.clone()
+        plan.step(a2, p2, A_out=a2, P_out=p2, n_steps=n)     # in place
+        torch.cuda.synchronize()
+        assert torch.equal(a2, ref[n][0]) and torch.equal(p2, ref[n][1]), n
+    # inputs untouched by out-of-place calls
+    assert np.array_equal(host(A), w.A) and np.array_equal(host(P), w.P)
+
+
+def test_saved_potentials_and_alpha(L, oracle):
+    w = inputs.test_world(80, 100, seed=118, n_blobs=6)
+    d = oracle.Desc.from_world(w)
+    plan = L.Plan(w)
+    saved = plan.new_saved()
+    gpu_step(plan, w.A, w.P, saved=saved)
+    u, a = plan.saved_views(saved)
+    r = oracle.step(d, w.A, w.P)
+    assert np.abs(host(u) - r["U"]).max() <= 2e-6
+    ok = (r["amb"] & 1) == 0
+    assert np.array_equal(host(a)[ok], r["alpha"][ok])
+
+
+def test_call_errors(L):
+    import torch
+    w = inputs.test_world(32, 32, seed=119, n_blobs=1)
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    with pytest.raises(L.LeniaError):
+        plan.step(A, P, A_out=A, P_out=torch.empty_like(P))     # mixed in/out of place
+    with pytest.raises(L.LeniaError):
+        plan.step(A, P, n_steps=2, saved=plan.new_saved())      # saved needs n_steps == 1
+    with pytest.raises(ValueError):
+        plan.step(A[:2], P)
+
+
+def test_full_size_sampled_windows(L, oracle):
+    """4096^2, 2000 blobs with their own genotypes, in the benchmark's launch
+    configuration: sampled windows (including ones across the torus seam)
+    checked cell by cell against the oracle run on the window plus its halo."""
+    import torch
+    w = inputs.config3()
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    A1, P1 = plan.step(A, P)
+    torch.cuda.synchronize()
+    A1h, P1h = host(A1), host(P1)
+    del A, P, A1, P1
+    rng = np.random.default_rng(5)
+    m = w.R + 1                          # halo: kernel radius + diffusion radius
+    hw = 48
+    starts = [(0, 0), (4096 - 20, 4096 - 30), (2048, 17)] + \
+             [tuple(rng.integers(0, 4096, 2)) for _ in range(3)]
+    for (y0, x0) in starts:
+        Aw = window(w.A, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
+        Pw = window(w.P, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
+        dw = oracle.Desc(hw + 2 * m, hw + 2 * m, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta,
+                         w.dt, 1, 1)
+        r = oracle.step(dw, Aw, Pw)
+        inner = (slice(m, m + hw), slice(m, m + hw))
+        rr = dict(A=r["A"][(slice(None),) + inner], P=r["P"][(slice(None), slice(None)) + inner],
+                  amb=r["amb"][inner])
+        compare_step(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw))
