@@ -94,6 +94,7 @@ struct WorldArgs {
     float* U_save;         // [NK][H][W] or null
     uint8_t* alpha_save;   // [H][W] or null
     const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
+    const float* wt;       // [n_orbits][C][8] the same weights by (orbit, source, slot)
     int H, W;
     int tiles_x, n_tiles;  // tile grid of this world
     float dt;

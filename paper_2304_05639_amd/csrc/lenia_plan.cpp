@@ -35,6 +35,7 @@ WorldArgs WorldPlan::args_template() const
     WorldArgs a;
     std::memset(&a, 0, sizeof(a));
     a.w = d_w;
+    a.wt = d_wt;
     a.H = H;
     a.W = W;
     a.dt = (float)dt;
@@ -126,7 +127,27 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
             }
         }
     }
+    // the same weights ordered (orbit, source channel, slot of the kernel among
+    // the kernels reading that channel), 8 slots per source
+    w.table = p->table;
+    const int kps = (p->table == TABLE_3x15) ? Table3x15::KPS : Table1x1::KPS;
+    std::vector<float> hwt((size_t)NO * w.C * 8, 0.f);
+    for (int t = 0; t < NO; ++t)
+        for (int sc = 0; sc < w.C; ++sc)
+            for (int j = 0; j < kps; ++j) {
+                const int k = (p->table == TABLE_3x15) ? Table3x15::kidx[sc][j] : Table1x1::kidx[sc][j];
+                hwt[((size_t)t * w.C + sc) * 8 + j] = hw[(size_t)k * NO + t];
+            }
     lenia_status st;
+    if ((st = dmalloc(p, (void**)&w.d_wt, hwt.size() * sizeof(float))) != LENIA_OK) return st;
+    {
+        float* keep_t = new float[hwt.size()];
+        std::memcpy(keep_t, hwt.data(), hwt.size() * sizeof(float));
+        host_keep.push_back(keep_t);
+        hipError_t e0 = hipMemcpyAsync(w.d_wt, keep_t, hwt.size() * sizeof(float),
+                                       hipMemcpyHostToDevice, s);
+        if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
+    }
     if ((st = dmalloc(p, (void**)&w.d_w, hw.size() * sizeof(float))) != LENIA_OK) return st;
     if ((st = dmalloc(p, (void**)&w.d_bcoef, hb.size() * sizeof(float))) != LENIA_OK) return st;
     // host copies stay alive until the stream has consumed them
@@ -320,8 +341,8 @@ static void default_tile(lenia_plan_t p)
     p->tile_y = tys[0];
     p->tile_x = txs[0];
     for (int i = 0; i < nc; ++i)
-        if (tys[i] == 32 && txs[i] == 64) {
-            p->tile_y = 32;
+        if (tys[i] == 8 && txs[i] == 64) {
+            p->tile_y = 8;
             p->tile_x = 64;
         }
 }

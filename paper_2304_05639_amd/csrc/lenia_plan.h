@@ -31,7 +31,9 @@ struct WorldPlan {
     std::vector<double> beta;      // [NK][3]
     std::vector<double> gm, gs, gh;
     int n_orbits = 0;
+    int table = 0;
     float* d_w = nullptr;          // [NK][n_orbits] orbit weights of K~_k
+    float* d_wt = nullptr;         // [n_orbits][C][8] by (orbit, source, slot)
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
     float* ws_P = nullptr;         // [3][NK][H][W] (gene update only)

@@ -18,7 +18,9 @@
 
 namespace lenia {
 
-constexpr int kThreads = 256;
+#ifndef LENIA_MIN_WAVES
+#define LENIA_MIN_WAVES 2   // minimum waves per SIMD the register budget must allow
+#endif
 
 // Block id -> tile id such that consecutive tiles land on the same XCD (the
 // dispatcher deals workgroups round-robin over the 8 XCDs, each with its own
@@ -31,71 +33,73 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb)
     return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-__device__ __forceinline__ int wrap_idx(int v, int n)
-{
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
-    return v;
-}
+// Kernel weights, per orbit t and source channel s: wt[(t * C + s) * 8 + j] is
+// the weight of the j-th kernel reading channel s (slot order of the table),
+// read through the constant address space: the index is uniform, so these
+// are scalar loads feeding the FMAs as SGPR operands.
+typedef const __attribute__((address_space(4))) float cfloat;
 
-// Sum of the A values over one tap orbit.  `b` points at the LDS cell that is
-// R rows above and R columns left of the output cell.
-template <int R, int PITCH, int A, int B>
-__device__ __forceinline__ float orbit_sum(const float* b)
+// Potentials of one cell: u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
+// The offsets are walked orbit by orbit (a, b), 1 <= a < R, 0 <= b <= a,
+// a^2 + b^2 < R^2, in the same order as Orbits<R>; each orbit's cells are
+// summed once per source channel and multiplied once per kernel.  `c` points
+// at the cell in the LDS tile of channel 0; channel s is CHS floats further.
+template <class T, int R, int PITCH, int CHS>
+__device__ __forceinline__ void conv_cell(const float* c, cfloat* __restrict__ wt,
+                                          float (&u)[T::NK])
 {
-    constexpr int c = R * PITCH + R;
-    if constexpr (B == 0) {
-        const float s0 = b[c + A * PITCH] + b[c - A * PITCH];
-        const float s1 = b[c + A] + b[c - A];
-        return s0 + s1;
-    } else if constexpr (A == B) {
-        const float s0 = b[c + A * PITCH + A] + b[c + A * PITCH - A];
-        const float s1 = b[c - A * PITCH + A] + b[c - A * PITCH - A];
-        return s0 + s1;
-    } else {
-        const float s0 = b[c + A * PITCH + B] + b[c + A * PITCH - B];
-        const float s1 = b[c - A * PITCH + B] + b[c - A * PITCH - B];
-        const float s2 = b[c + B * PITCH + A] + b[c + B * PITCH - A];
-        const float s3 = b[c - B * PITCH + A] + b[c - B * PITCH - A];
-        return (s0 + s1) + (s2 + s3);
+    float acc[T::C][T::KPS];
+#pragma unroll
+    for (int s = 0; s < T::C; ++s)
+#pragma unroll
+        for (int j = 0; j < T::KPS; ++j) acc[s][j] = 0.f;
+    int t = 0;
+#pragma unroll 1
+    for (int a = 1; a < R; ++a) {
+#pragma unroll 1
+        for (int b = 0; b <= a && a * a + b * b < R * R; ++b, ++t) {
+            float sum[T::C];
+            if (b == 0) {
+                const float* p0 = c + a * PITCH;
+                const float* p1 = c - a * PITCH;
+                const float* p2 = c + a;
+                const float* p3 = c - a;
+#pragma unroll
+                for (int s = 0; s < T::C; ++s)
+                    sum[s] = (p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS]);
+            } else if (b == a) {
+                const float* p0 = c + a * PITCH + a;
+                const float* p1 = c + a * PITCH - a;
+                const float* p2 = c - a * PITCH + a;
+                const float* p3 = c - a * PITCH - a;
+#pragma unroll
+                for (int s = 0; s < T::C; ++s)
+                    sum[s] = (p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS]);
+            } else {
+                const float* p0 = c + a * PITCH + b;
+                const float* p1 = c + a * PITCH - b;
+                const float* p2 = c - a * PITCH + b;
+                const float* p3 = c - a * PITCH - b;
+                const float* p4 = c + b * PITCH + a;
+                const float* p5 = c + b * PITCH - a;
+                const float* p6 = c - b * PITCH + a;
+                const float* p7 = c - b * PITCH - a;
+#pragma unroll
+                for (int s = 0; s < T::C; ++s)
+                    sum[s] = ((p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS])) +
+                             ((p4[s * CHS] + p5[s * CHS]) + (p6[s * CHS] + p7[s * CHS]));
+            }
+            cfloat* w = wt + t * (T::C * 8);
+#pragma unroll
+            for (int s = 0; s < T::C; ++s)
+#pragma unroll
+                for (int j = 0; j < T::KPS; ++j) acc[s][j] = fmaf(w[s * 8 + j], sum[s], acc[s][j]);
+        }
     }
-}
-
-template <class T, int R, int PITCH, int CHS, int S, int... I>
-__device__ __forceinline__ void conv_source(const float* base, const float* __restrict__ w,
-                                            float (&acc)[T::KPS],
-                                            std::integer_sequence<int, I...>)
-{
-    using O = Orbits<R>;
-    constexpr int NO = O::N;
-    (
-        [&] {
-            const float sum = orbit_sum<R, PITCH, O::tab.a[I], O::tab.b[I]>(base + S * CHS);
 #pragma unroll
-            for (int j = 0; j < T::KPS; ++j)
-                acc[j] = fmaf(w[T::kidx[S][j] * NO + I], sum, acc[j]);
-        }(),
-        ...);
-}
-
-template <class T, int R, int PITCH, int CHS, int S>
-__device__ __forceinline__ void conv_one_source(const float* base, const float* __restrict__ w,
-                                                float (&u)[T::NK])
-{
-    float acc[T::KPS];
+    for (int s = 0; s < T::C; ++s)
 #pragma unroll
-    for (int j = 0; j < T::KPS; ++j) acc[j] = 0.f;
-    conv_source<T, R, PITCH, CHS, S>(base, w, acc,
-                                     std::make_integer_sequence<int, Orbits<R>::N>{});
-#pragma unroll
-    for (int j = 0; j < T::KPS; ++j) u[T::kidx[S][j]] = acc[j];
-}
-
-template <class T, int R, int PITCH, int CHS, int... S>
-__device__ __forceinline__ void conv_all(const float* base, const float* __restrict__ w,
-                                         float (&u)[T::NK], std::integer_sequence<int, S...>)
-{
-    (conv_one_source<T, R, PITCH, CHS, S>(base, w, u), ...);
+        for (int j = 0; j < T::KPS; ++j) u[T::kidx[s][j]] = acc[s][j];
 }
 
 __device__ __forceinline__ float growth(float u, float m, float s, float h)
@@ -122,28 +126,55 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int txi = tile - tyi * wd.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
 
-    // 1. stage A (+halo, wrapped)
-    for (int i = threadIdx.x; i < T::C * PY * PX; i += kThreads) {
-        const int c = i / (PY * PX);
-        const int r = i - c * (PY * PX);
-        const int yy = r / PX;
-        const int xx = r - yy * PX;
-        const int gy = wrap_idx(y0 + yy - R, H);
-        const int gx = wrap_idx(x0 + xx - R, W);
-        sA[c * CHS + yy * PITCH + xx] = wd.A[(size_t)c * HW + (size_t)gy * W + gx];
+    // 1. stage A (+halo, wrapped) with all of a thread's loads in flight at once
+    {
+        constexpr int NT = TY * TX;
+        constexpr int NS = T::C * PY * PX;
+        constexpr int IT = (NS + NT - 1) / NT;
+        // a single wrap suffices unless the torus is smaller than tile + halo
+        const bool single_wrap = (H >= TY + R) && (W >= TX + R);
+        float v[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int i = threadIdx.x + it * NT;
+            if (i < NS) {
+                const int c = i / (PY * PX);
+                const int r = i - c * (PY * PX);
+                const int yy = r / PX;
+                const int xx = r - yy * PX;
+                int gy = y0 + yy - R, gx = x0 + xx - R;
+                if (single_wrap) {
+                    gy += (gy < 0) ? H : 0;
+                    gy -= (gy >= H) ? H : 0;
+                    gx += (gx < 0) ? W : 0;
+                    gx -= (gx >= W) ? W : 0;
+                } else {
+                    gy = ((gy % H) + H) % H;
+                    gx = ((gx % W) + W) % W;
+                }
+                v[it] = wd.A[(size_t)c * HW + (size_t)gy * W + gx];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int i = threadIdx.x + it * NT;
+            if (i < NS) sA[i] = v[it];
+        }
     }
     __syncthreads();
 
-    for (int cell = threadIdx.x; cell < TY * TX; cell += kThreads) {
+    // one output cell per thread (no cell loop: nothing for the compiler to
+    // hoist across cells)
+    {
+        const int cell = threadIdx.x;
         const int ly = cell / TX;
         const int lx = cell - ly * TX;
         const int gy = y0 + ly, gx = x0 + lx;
-        if (gy >= H || gx >= W) continue;
+        if (gy >= H || gx >= W) return;
 
         // 2. potentials
         float u[NK];
-        conv_all<T, R, PITCH, CHS>(sA + ly * PITCH + lx, wd.w, u,
-                                   std::make_integer_sequence<int, T::C>{});
+        conv_cell<T, R, PITCH, CHS>(sA + (ly + R) * PITCH + (lx + R), (cfloat*)wd.wt, u);
 
         const size_t oc = (size_t)gy * W + gx;
         const float eps = wd.eps;
@@ -159,19 +190,23 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             const int xp = (gx == W - 1) ? 0 : gx + 1;
             const size_t ou = (size_t)ym * W + gx, od = (size_t)yp * W + gx;
             const size_t ol = (size_t)gy * W + xm, orr = (size_t)gy * W + xp;
+            // alpha needs every potential above the cutoff; where one is not,
+            // the genes are masked to 0 and need not be read at all
             bool alpha = true;
 #pragma unroll
             for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
             float pd[NP];
+            if (alpha) {
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const float* pl = wd.P + (size_t)q * HW;
-                const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
-                const float num = (((vu + vl) + vc) + vr) + vd;
-                const int n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
-                const float v = (n > 0) ? clip01(num / (float)n) : 0.f;
-                pd[q] = v;
-                alpha = alpha && (v > eps);
+                for (int q = 0; q < NP; ++q) {
+                    const float* pl = wd.P + (size_t)q * HW;
+                    const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
+                    const float num = (((vu + vl) + vc) + vr) + vd;
+                    const int n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
+                    const float v = (n > 0) ? clip01(num / (float)n) : 0.f;
+                    pd[q] = v;
+                    alpha = alpha && (v > eps);
+                }
             }
             // 3b. localized growth and update
             if (alpha) {
@@ -207,7 +242,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
 }
 
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void step_kernel(WorldArgs wd, int mode)
+__global__ __launch_bounds__(TY * TX, LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
 {
     __shared__ float sA[T::C * (TY + 2 * R) * (TX + 2 * R)];
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA);
@@ -215,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(WorldArgs wd, int mode)
 
 // Persistent form: a fixed grid walks the (world, tile) work list.
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__(kThreads) void step_batch_kernel(BatchList bl, int mode)
+__global__ __launch_bounds__(TY * TX, LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
     __shared__ float sA[T::C * (TY + 2 * R) * (TX + 2 * R)];
     for (int i = blockIdx.x; i < bl.n_items; i += gridDim.x) {
@@ -228,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void step_batch_kernel(BatchList bl, int 
 template <class T, int R, int TY, int TX>
 hipError_t launch_step(const WorldArgs& w, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL((step_kernel<T, R, TY, TX>), dim3(w.n_tiles), dim3(kThreads), 0, s, w,
+    hipLaunchKernelGGL((step_kernel<T, R, TY, TX>), dim3(w.n_tiles), dim3(TY * TX), 0, s, w,
                        mode);
     return hipGetLastError();
 }
@@ -236,7 +271,7 @@ hipError_t launch_step(const WorldArgs& w, int mode, hipStream_t s)
 template <class T, int R, int TY, int TX>
 hipError_t launch_batch(const BatchList& b, int mode, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(grid), dim3(kThreads), 0, s, b,
+    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(grid), dim3(TY * TX), 0, s, b,
                        mode);
     return hipGetLastError();
 }
@@ -251,14 +286,14 @@ struct Entry {
     {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>}
 
 static const Entry kEntries[] = {
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 4, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 32),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 64),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 32, 64),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 32, 32),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 64, 64),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 32, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 8, 64),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 8, 64),
     LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 64),
-    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 32, 64),
-    LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 32, 64),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 8, 64),
 };
 
 step_launch_fn find_step_launcher(int table, int R, int ty, int tx)
