@@ -131,12 +131,27 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
     // the kernels reading that channel), 8 slots per source
     w.table = p->table;
     const int kps = (p->table == TABLE_3x15) ? Table3x15::KPS : Table1x1::KPS;
+    // orbit order of the step kernel's loops: axis (a,0), diagonal (a,a),
+    // then general (a,b) with 0 < b < a, each by increasing a (then b)
+    std::vector<int> korder;
+    {
+        auto index_of = [&](int a, int b) {
+            for (int t = 0; t < NO; ++t)
+                if (oa[t] == a && ob[t] == b) return t;
+            return -1;
+        };
+        for (int a = 1; a < w.R; ++a) korder.push_back(index_of(a, 0));
+        for (int a = 1; 2 * a * a < w.R * w.R; ++a) korder.push_back(index_of(a, a));
+        for (int a = 2; a < w.R; ++a)
+            for (int b = 1; b < a && a * a + b * b < w.R * w.R; ++b) korder.push_back(index_of(a, b));
+    }
+    if ((int)korder.size() != NO) return set_error(LENIA_ERR_STATE, "orbit enumeration mismatch");
     std::vector<float> hwt((size_t)NO * w.C * 8, 0.f);
-    for (int t = 0; t < NO; ++t)
+    for (int i = 0; i < NO; ++i)
         for (int sc = 0; sc < w.C; ++sc)
             for (int j = 0; j < kps; ++j) {
                 const int k = (p->table == TABLE_3x15) ? Table3x15::kidx[sc][j] : Table1x1::kidx[sc][j];
-                hwt[((size_t)t * w.C + sc) * 8 + j] = hw[(size_t)k * NO + t];
+                hwt[((size_t)i * w.C + sc) * 8 + j] = hw[(size_t)k * NO + korder[i]];
             }
     lenia_status st;
     if ((st = dmalloc(p, (void**)&w.d_wt, hwt.size() * sizeof(float))) != LENIA_OK) return st;
@@ -341,9 +356,9 @@ static void default_tile(lenia_plan_t p)
     p->tile_y = tys[0];
     p->tile_x = txs[0];
     for (int i = 0; i < nc; ++i)
-        if (tys[i] == 8 && txs[i] == 64) {
-            p->tile_y = 8;
-            p->tile_x = 64;
+        if (tys[i] == 16 && txs[i] == 32) {
+            p->tile_y = 16;
+            p->tile_x = 32;
         }
 }
 

@@ -39,86 +39,224 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb)
 // are scalar loads feeding the FMAs as SGPR operands.
 typedef const __attribute__((address_space(4))) float cfloat;
 
-// Potentials of one cell: u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
-// The offsets are walked orbit by orbit (a, b), 1 <= a < R, 0 <= b <= a,
-// a^2 + b^2 < R^2, in the same order as Orbits<R>; each orbit's cells are
-// summed once per source channel and multiplied once per kernel.  `c` points
-// at the cell in the LDS tile of channel 0; channel s is CHS floats further.
-template <class T, int R, int PITCH, int CHS>
-__device__ __forceinline__ void conv_cell(const float* c, cfloat* __restrict__ wt,
-                                          float (&u)[T::NK])
+// Potentials of a vertical pair of cells (c and c + PITCH):
+//   u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
+// The offsets are walked orbit by orbit in three branch-free loops, in the
+// order of the weight table: axis orbits (a, 0), diagonal orbits (a, a), then
+// general orbits (a, b), 0 < b < a (all with a^2 + b^2 < R^2).  Each orbit's
+// cells are summed once per source channel and multiplied once per kernel.
+// `c` points at the upper cell in the LDS tile of channel 0; channel s is CHS
+// floats further.
+template <class T, int PITCH, int CHS>
+__device__ __forceinline__ void orbit_fma(float (&acc)[2][T::C][T::KPS], const float (&sum)[2][T::C],
+                                          cfloat* w)
 {
-    float acc[T::C][T::KPS];
 #pragma unroll
     for (int s = 0; s < T::C; ++s)
 #pragma unroll
-        for (int j = 0; j < T::KPS; ++j) acc[s][j] = 0.f;
-    int t = 0;
+        for (int j = 0; j < T::KPS; ++j) {
+            const float wj = w[s * 8 + j];
+            acc[0][s][j] = fmaf(wj, sum[0][s], acc[0][s][j]);
+            acc[1][s][j] = fmaf(wj, sum[1][s], acc[1][s][j]);
+        }
+}
+
+// Sum over one tap of both cells and every channel: p points at the tap of
+// the upper cell in channel 0; channel s is CHS floats further, the lower cell
+// PITCH floats further.  With CHS and PITCH multiples of 64 floats all six
+// values come from one address register (ds_read2st64 pairs).
+template <class T, int PITCH, int CHS>
+__device__ __forceinline__ void tap_add(float (&sum)[2][T::C], const float* p)
+{
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < T::C; ++s) sum[q][s] += p[s * CHS + q * PITCH];
+}
+
+template <class T, int PITCH, int CHS>
+__device__ __forceinline__ void tap_load(float (&v)[2][T::C], const float* p)
+{
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < T::C; ++s) v[q][s] = p[s * CHS + q * PITCH];
+}
+
+// sum = (t0 + t1) + (t2 + t3) for each (cell, channel)
+template <class T, int PITCH, int CHS>
+__device__ __forceinline__ void quad_sum(float (&sum)[2][T::C], const float* p0, const float* p1,
+                                         const float* p2, const float* p3)
+{
+    float v0[2][T::C], v1[2][T::C], v2[2][T::C], v3[2][T::C];
+    tap_load<T, PITCH, CHS>(v0, p0);
+    tap_load<T, PITCH, CHS>(v1, p1);
+    tap_load<T, PITCH, CHS>(v2, p2);
+    tap_load<T, PITCH, CHS>(v3, p3);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < T::C; ++s) sum[q][s] = (v0[q][s] + v1[q][s]) + (v2[q][s] + v3[q][s]);
+}
+
+template <class T, int R, int PITCH, int CHS>
+__device__ __forceinline__ void conv_pair(const float* c, cfloat* __restrict__ wt,
+                                          float (&u)[2][T::NK])
+{
+    constexpr int WS = T::C * 8;   // weights per orbit
+    float acc[2][T::C][T::KPS];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int s = 0; s < T::C; ++s)
+#pragma unroll
+            for (int j = 0; j < T::KPS; ++j) acc[q][s][j] = 0.f;
+    cfloat* w = wt;
+    // axis orbits: (+-a, 0), (0, +-a)
 #pragma unroll 1
-    for (int a = 1; a < R; ++a) {
+    for (int a = 1; a < R; ++a, w += WS) {
+        float sum[2][T::C];
+        quad_sum<T, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
+        orbit_fma<T, PITCH, CHS>(acc, sum, w);
+    }
+    // diagonal orbits: (+-a, +-a)
 #pragma unroll 1
-        for (int b = 0; b <= a && a * a + b * b < R * R; ++b, ++t) {
-            float sum[T::C];
-            if (b == 0) {
-                const float* p0 = c + a * PITCH;
-                const float* p1 = c - a * PITCH;
-                const float* p2 = c + a;
-                const float* p3 = c - a;
+    for (int a = 1; 2 * a * a < R * R; ++a, w += WS) {
+        float sum[2][T::C];
+        quad_sum<T, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a, c - a * PITCH + a,
+                                c - a * PITCH - a);
+        orbit_fma<T, PITCH, CHS>(acc, sum, w);
+    }
+    // general orbits: (+-a, +-b), (+-b, +-a), 0 < b < a
+#pragma unroll 1
+    for (int a = 2; a < R; ++a) {
+#pragma unroll 1
+        for (int b = 1; b < a && a * a + b * b < R * R; ++b, w += WS) {
+            float s0[2][T::C], s1[2][T::C];
+            quad_sum<T, PITCH, CHS>(s0, c + a * PITCH + b, c + a * PITCH - b, c - a * PITCH + b,
+                                    c - a * PITCH - b);
+            quad_sum<T, PITCH, CHS>(s1, c + b * PITCH + a, c + b * PITCH - a, c - b * PITCH + a,
+                                    c - b * PITCH - a);
+            float sum[2][T::C];
 #pragma unroll
-                for (int s = 0; s < T::C; ++s)
-                    sum[s] = (p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS]);
-            } else if (b == a) {
-                const float* p0 = c + a * PITCH + a;
-                const float* p1 = c + a * PITCH - a;
-                const float* p2 = c - a * PITCH + a;
-                const float* p3 = c - a * PITCH - a;
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int s = 0; s < T::C; ++s)
-                    sum[s] = (p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS]);
-            } else {
-                const float* p0 = c + a * PITCH + b;
-                const float* p1 = c + a * PITCH - b;
-                const float* p2 = c - a * PITCH + b;
-                const float* p3 = c - a * PITCH - b;
-                const float* p4 = c + b * PITCH + a;
-                const float* p5 = c + b * PITCH - a;
-                const float* p6 = c - b * PITCH + a;
-                const float* p7 = c - b * PITCH - a;
-#pragma unroll
-                for (int s = 0; s < T::C; ++s)
-                    sum[s] = ((p0[s * CHS] + p1[s * CHS]) + (p2[s * CHS] + p3[s * CHS])) +
-                             ((p4[s * CHS] + p5[s * CHS]) + (p6[s * CHS] + p7[s * CHS]));
-            }
-            cfloat* w = wt + t * (T::C * 8);
-#pragma unroll
-            for (int s = 0; s < T::C; ++s)
-#pragma unroll
-                for (int j = 0; j < T::KPS; ++j) acc[s][j] = fmaf(w[s * 8 + j], sum[s], acc[s][j]);
+                for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
+            orbit_fma<T, PITCH, CHS>(acc, sum, w);
         }
     }
 #pragma unroll
-    for (int s = 0; s < T::C; ++s)
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int j = 0; j < T::KPS; ++j) u[T::kidx[s][j]] = acc[s][j];
+        for (int s = 0; s < T::C; ++s)
+#pragma unroll
+            for (int j = 0; j < T::KPS; ++j) u[q][T::kidx[s][j]] = acc[q][s][j];
 }
 
+// G(u; m, s, h) = h (2 exp(-(u-m)^2 / (2 s^2)) - 1), with the hardware
+// reciprocal and exponential (a few ulp; the exponent's error only matters
+// where the exponential is far below the state tolerance).
 __device__ __forceinline__ float growth(float u, float m, float s, float h)
 {
     const float d = u - m;
-    return h * (2.f * expf(-(d * d) / (2.f * s * s)) - 1.f);
+    const float inv = __builtin_amdgcn_rcpf(2.f * s * s);
+    return h * (2.f * __expf(-(d * d) * inv) - 1.f);
 }
 
 __device__ __forceinline__ float clip01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
 
-// One tile of one world.
+// Gene diffusion, alpha mask, growth and update of one cell (gy, gx) given its
+// potentials u and its current state a[c]; writes A' and P' (and the saved
+// potentials / alpha when requested).
+template <class T>
+__device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, const float (&u)[T::NK],
+                                              const float (&a)[T::C], int gy, int gx)
+{
+    constexpr int NK = T::NK;
+    constexpr int NP = 3 * NK;
+    const int H = wd.H, W = wd.W;
+    const size_t HW = (size_t)H * W;
+    // in-plane offsets fit 32 bits (H, W <= 65536 and a plane < 2^32 bytes is
+    // required); plane bases are uniform, so loads use a scalar base
+    const uint32_t oc = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+    const float eps = wd.eps;
+    float sum[T::C];
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) sum[c] = 0.f;
+
+    if (mode == MODE_LOCAL_UPDATE) {
+        // alpha needs every potential above the cutoff; where one is not, the
+        // genes are masked to 0 and need not be read at all
+        bool alpha = true;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
+        float pd[NP];
+        if (alpha) {
+            // diffusion of every gene plane over the r = 1 disk
+            const int ym = (gy == 0) ? H - 1 : gy - 1;
+            const int yp = (gy == H - 1) ? 0 : gy + 1;
+            const int xm = (gx == 0) ? W - 1 : gx - 1;
+            const int xp = (gx == W - 1) ? 0 : gx + 1;
+            const uint32_t ou = (uint32_t)ym * W + gx, od = (uint32_t)yp * W + gx;
+            const uint32_t ol = (uint32_t)gy * W + xm, orr = (uint32_t)gy * W + xp;
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const float* pl = wd.P + (size_t)q * HW;
+                const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
+                const float num = (((vu + vl) + vc) + vr) + vd;
+                const int n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
+                const float v = (n > 0) ? clip01(num * __builtin_amdgcn_rcpf((float)n)) : 0.f;
+                pd[q] = v;
+                alpha = alpha && (v > eps);
+            }
+        }
+        if (alpha) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k)
+                sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+        }
+#pragma unroll
+        for (int q = 0; q < NP; ++q) (wd.P_out + (size_t)q * HW)[oc] = alpha ? pd[q] : 0.f;
+        if (wd.alpha_save) wd.alpha_save[oc] = alpha ? 1 : 0;
+    } else if (mode == MODE_LOCAL_READONLY) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k)
+            sum[T::dst[k]] += growth(u[k], wd.P[(size_t)k * HW + oc], wd.P[(size_t)(NK + k) * HW + oc],
+                                     wd.P[(size_t)(2 * NK + k) * HW + oc]);
+        if (wd.alpha_save) wd.alpha_save[oc] = 1;
+    } else {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], wd.gm[k], wd.gs[k], wd.gh[k]);
+        if (wd.alpha_save) wd.alpha_save[oc] = 1;
+    }
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) (wd.A_out + (size_t)c * HW)[oc] = clip01(a[c] + wd.dt * sum[c]);
+    if (wd.U_save) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) (wd.U_save + (size_t)k * HW)[oc] = u[k];
+    }
+}
+
+template <int TY, int TX>
+constexpr int step_threads() { return TY * TX / 2; }
+
+// LDS row pitch of a staged tile: tile width + halo, rounded up to a multiple
+// of 64 floats so that every channel / row offset is a ds_read2st64 offset.
+template <int R, int TX>
+constexpr int tile_pitch() { return ((TX + 2 * R + 63) / 64) * 64; }
+
+template <class T, int R, int TY, int TX>
+constexpr int tile_lds_floats() { return T::C * (TY + 2 * R) * tile_pitch<R, TX>(); }
+
+// One tile of one world.  Each thread owns a vertical pair of cells.
 template <class T, int R, int TY, int TX>
 __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA)
 {
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
-    constexpr int PITCH = PX;
+    constexpr int PITCH = tile_pitch<R, TX>();
     constexpr int CHS = PY * PITCH;
     constexpr int NK = T::NK;
-    constexpr int NP = 3 * NK;
+    constexpr int NT = step_threads<TY, TX>();
 
     const int H = wd.H, W = wd.W;
     const size_t HW = (size_t)H * W;
@@ -126,22 +264,20 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int txi = tile - tyi * wd.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
 
-    // 1. stage A (+halo, wrapped) with all of a thread's loads in flight at once
+    // 1. stage A (+halo, wrapped) with all of a thread's loads in flight at once;
+    // the index arithmetic of a halo position is shared by the channels
     {
-        constexpr int NT = TY * TX;
-        constexpr int NS = T::C * PY * PX;
-        constexpr int IT = (NS + NT - 1) / NT;
+        constexpr int NG = PY * PX;
+        constexpr int IT = (NG + NT - 1) / NT;
         // a single wrap suffices unless the torus is smaller than tile + halo
         const bool single_wrap = (H >= TY + R) && (W >= TX + R);
-        float v[IT];
+        float v[IT][T::C];
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int i = threadIdx.x + it * NT;
-            if (i < NS) {
-                const int c = i / (PY * PX);
-                const int r = i - c * (PY * PX);
-                const int yy = r / PX;
-                const int xx = r - yy * PX;
+            if (i < NG) {
+                const int yy = i / PX;
+                const int xx = i - yy * PX;
                 int gy = y0 + yy - R, gx = x0 + xx - R;
                 if (single_wrap) {
                     gy += (gy < 0) ? H : 0;
@@ -152,107 +288,55 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
                     gy = ((gy % H) + H) % H;
                     gx = ((gx % W) + W) % W;
                 }
-                v[it] = wd.A[(size_t)c * HW + (size_t)gy * W + gx];
+                const uint32_t o = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+#pragma unroll
+                for (int ch = 0; ch < T::C; ++ch) v[it][ch] = (wd.A + (size_t)ch * HW)[o];
             }
         }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int i = threadIdx.x + it * NT;
-            if (i < NS) sA[i] = v[it];
+            if (i < NG) {
+                const int yy = i / PX;
+                const int xx = i - yy * PX;
+#pragma unroll
+                for (int ch = 0; ch < T::C; ++ch) sA[ch * CHS + yy * PITCH + xx] = v[it][ch];
+            }
         }
     }
     __syncthreads();
 
-    // one output cell per thread (no cell loop: nothing for the compiler to
-    // hoist across cells)
-    {
-        const int cell = threadIdx.x;
-        const int ly = cell / TX;
-        const int lx = cell - ly * TX;
-        const int gy = y0 + ly, gx = x0 + lx;
-        if (gy >= H || gx >= W) return;
-
-        // 2. potentials
-        float u[NK];
-        conv_cell<T, R, PITCH, CHS>(sA + (ly + R) * PITCH + (lx + R), (cfloat*)wd.wt, u);
-
-        const size_t oc = (size_t)gy * W + gx;
-        const float eps = wd.eps;
-        float sum[T::C];
+    // 2. potentials of the thread's two cells, 3. their epilogues
+    const int ly = 2 * (threadIdx.x / TX);
+    const int lx = threadIdx.x % TX;
+    const int gy = y0 + ly, gx = x0 + lx;
+    if (gy >= H || gx >= W) return;
+    const float* c = sA + (ly + R) * PITCH + (lx + R);
+    float u[2][NK];
+    conv_pair<T, R, PITCH, CHS>(c, (cfloat*)wd.wt, u);
 #pragma unroll
-        for (int c = 0; c < T::C; ++c) sum[c] = 0.f;
-
-        if (mode == MODE_LOCAL_UPDATE) {
-            // 3a. diffusion of every gene plane, alpha
-            const int ym = (gy == 0) ? H - 1 : gy - 1;
-            const int yp = (gy == H - 1) ? 0 : gy + 1;
-            const int xm = (gx == 0) ? W - 1 : gx - 1;
-            const int xp = (gx == W - 1) ? 0 : gx + 1;
-            const size_t ou = (size_t)ym * W + gx, od = (size_t)yp * W + gx;
-            const size_t ol = (size_t)gy * W + xm, orr = (size_t)gy * W + xp;
-            // alpha needs every potential above the cutoff; where one is not,
-            // the genes are masked to 0 and need not be read at all
-            bool alpha = true;
+    for (int q = 0; q < 2; ++q) {
+        if (gy + q < H) {
+            float a[T::C];
 #pragma unroll
-            for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
-            float pd[NP];
-            if (alpha) {
-#pragma unroll
-                for (int q = 0; q < NP; ++q) {
-                    const float* pl = wd.P + (size_t)q * HW;
-                    const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
-                    const float num = (((vu + vl) + vc) + vr) + vd;
-                    const int n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
-                    const float v = (n > 0) ? clip01(num / (float)n) : 0.f;
-                    pd[q] = v;
-                    alpha = alpha && (v > eps);
-                }
-            }
-            // 3b. localized growth and update
-            if (alpha) {
-#pragma unroll
-                for (int k = 0; k < NK; ++k)
-                    sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
-            }
-#pragma unroll
-            for (int q = 0; q < NP; ++q) wd.P_out[(size_t)q * HW + oc] = alpha ? pd[q] : 0.f;
-            if (wd.alpha_save) wd.alpha_save[oc] = alpha ? 1 : 0;
-        } else if (mode == MODE_LOCAL_READONLY) {
-#pragma unroll
-            for (int k = 0; k < NK; ++k)
-                sum[T::dst[k]] += growth(u[k], wd.P[(size_t)k * HW + oc],
-                                         wd.P[(size_t)(NK + k) * HW + oc],
-                                         wd.P[(size_t)(2 * NK + k) * HW + oc]);
-            if (wd.alpha_save) wd.alpha_save[oc] = 1;
-        } else {
-#pragma unroll
-            for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], wd.gm[k], wd.gs[k], wd.gh[k]);
-            if (wd.alpha_save) wd.alpha_save[oc] = 1;
-        }
-#pragma unroll
-        for (int c = 0; c < T::C; ++c) {
-            const float a = sA[c * CHS + (ly + R) * PITCH + (lx + R)];
-            wd.A_out[(size_t)c * HW + oc] = clip01(a + wd.dt * sum[c]);
-        }
-        if (wd.U_save) {
-#pragma unroll
-            for (int k = 0; k < NK; ++k) wd.U_save[(size_t)k * HW + oc] = u[k];
+            for (int ch = 0; ch < T::C; ++ch) a[ch] = c[ch * CHS + q * PITCH];
+            epilogue_cell<T>(wd, mode, u[q], a, gy + q, gx);
         }
     }
 }
 
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__(TY * TX, LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
+__global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
 {
-    __shared__ float sA[T::C * (TY + 2 * R) * (TX + 2 * R)];
+    __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA);
 }
 
 // Persistent form: a fixed grid walks the (world, tile) work list.
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__(TY * TX, LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
+__global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
-    __shared__ float sA[T::C * (TY + 2 * R) * (TX + 2 * R)];
+    __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
     for (int i = blockIdx.x; i < bl.n_items; i += gridDim.x) {
         const int2 it = bl.items[i];
         process_tile<T, R, TY, TX>(bl.worlds[it.x], it.y, mode, sA);
@@ -263,7 +347,7 @@ __global__ __launch_bounds__(TY * TX, LENIA_MIN_WAVES) void step_batch_kernel(Ba
 template <class T, int R, int TY, int TX>
 hipError_t launch_step(const WorldArgs& w, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL((step_kernel<T, R, TY, TX>), dim3(w.n_tiles), dim3(TY * TX), 0, s, w,
+    hipLaunchKernelGGL((step_kernel<T, R, TY, TX>), dim3(w.n_tiles), dim3(step_threads<TY, TX>()), 0, s, w,
                        mode);
     return hipGetLastError();
 }
@@ -271,7 +355,7 @@ hipError_t launch_step(const WorldArgs& w, int mode, hipStream_t s)
 template <class T, int R, int TY, int TX>
 hipError_t launch_batch(const BatchList& b, int mode, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(grid), dim3(TY * TX), 0, s, b,
+    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(grid), dim3(step_threads<TY, TX>()), 0, s, b,
                        mode);
     return hipGetLastError();
 }
@@ -286,14 +370,15 @@ struct Entry {
     {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>}
 
 static const Entry kEntries[] = {
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 64),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 4, 64),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 32),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 32, 32),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 32),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 64),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 8, 64),
-    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 8, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 16, 32),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 32),
     LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 64),
-    LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 8, 64),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 16, 32),
 };
 
 step_launch_fn find_step_launcher(int table, int R, int ty, int tx)

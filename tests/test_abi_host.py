@@ -81,7 +81,7 @@ def test_unsupported_descriptors(changes):
 def test_unknown_tile_and_flags():
     w = inputs.test_world(32, 32, seed=2, n_blobs=1)
     assert _ok(w, tile=(24, 24)) == L.ERR_UNSUPPORTED
-    assert _ok(w, tile=(8, 64)) == L.OK
+    assert _ok(w, tile=(16, 32)) == L.OK
     b = L.DescBuilder(w)
     b.desc.flags = 0x80
     import ctypes
