@@ -1,7 +1,381 @@
-// Adjoint (vector-Jacobian product) of one Lenia step.
+// Adjoint (vector-Jacobian product) of one Lenia step on gfx950.
+//
+// Forward at a cell (see lenia_step.hip):  P_d = diffusion of P (Section 2.3),
+// u_k = K~_k * A_src(k) (Section 2.1), alpha = all u_k > eps and all P_d > eps
+// (Section 2.2), g_k = alpha h_k (2 e_k - 1), e_k = exp(-(u_k - m_k)^2/(2 s_k^2))
+// with (m, s, h) = alpha P_d (Section 2.4), z_c = A_c + dt sum_{dst(k)=c} g_k,
+// A'_c = clip01(z_c), P' = alpha P_d.  Given cotangents (gA', gP') the adjoint
+// is, with alpha and the diffusion counts n held fixed (piecewise constant) and
+// the clips' inclusive subgradients:
+//   zbar_c   = gA'_c [0 <= z_c <= 1]                     -> gA_c (direct term)
+//   ubar_k   = dt zbar_dst(k) (-2 h e (u-m)/s^2)
+//   Pbar_d   = alpha (gP' + dt zbar_dst(k) (dg/dm, dg/ds, dg/dh))
+//   numbar   = Pbar_d [n > 0 and 0 <= num/n <= 1] / n
+//   gA_c    += sum_{src(k)=c} K~_k (x) ubar_k  (K~ even: correlation again)
+//   gP(y)    = sum over the r = 1 disk of numbar(y + d)
+//   dL/dbeta_{k,i} = sum_t G_k(t) bcoef_{k,i}(t),  G_k(t) = <ubar_k, orbit-sum_t A_src>
+// Three kernels: a per-cell pass, a tiled gather pass (convolution transpose,
+// diffusion transpose, shell-height partials per tile), and a fixed-order
+// reduction of the partials.  No float atomics: results are deterministic.
+#include <utility>
+
 #include "lenia.h"
+#include "lenia_device.h"
 #include "lenia_internal.h"
 #include "lenia_plan.h"
+
+namespace lenia {
+
+struct BwdArgs {
+    const float* A;          // A_t    [C][H][W]
+    const float* P;          // P_t    [3NK][H][W]
+    const float* U;          // saved potentials [NK][H][W]
+    const uint8_t* alpha;    // saved alpha [H][W]
+    const float* gA1;        // gA_next [C][H][W]
+    const float* gP1;        // gP_next [3NK][H][W] or null (zero)
+    float* gA;               // gA_t (written by the cell pass, completed by the gather pass)
+    float* gP;               // gP_t
+    float* ubar;             // workspace [NK][H][W]
+    float* numbar;           // workspace [3NK][H][W] (gene update only)
+    float* part;             // workspace [n_tiles][NK][3]
+    const float* wt;         // orbit weights [NO][C][8] in the step kernel's orbit order
+    const float* bt;         // beta coefficients [NK][3][NO] in the same orbit order
+    int H, W, tiles_x, n_tiles;
+    float dt, eps;
+    int mode;
+};
+
+// ---------------------------------------------------------------------------
+// 1. per-cell pass
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
+{
+    constexpr int NK = T::NK, NP = 3 * NK;
+    const int H = b.H, W = b.W;
+    const uint32_t HW = (uint32_t)H * (uint32_t)W;
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= HW) return;
+    const int gy = (int)(idx / (uint32_t)W), gx = (int)(idx - (uint32_t)gy * W);
+    const float eps = b.eps, dt = b.dt;
+    const bool update = (b.mode == MODE_LOCAL_UPDATE);
+    const bool alpha = update ? (b.alpha[idx] != 0) : true;
+
+    float a[T::C], zb[T::C];
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) a[c] = (b.A + (size_t)c * HW)[idx];
+
+    if (!alpha) {
+        // no growth: z = A, P' = 0
+#pragma unroll
+        for (int c = 0; c < T::C; ++c) {
+            const float g1 = (b.gA1 + (size_t)c * HW)[idx];
+            (b.gA + (size_t)c * HW)[idx] = (a[c] >= 0.f && a[c] <= 1.f) ? g1 : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) (b.ubar + (size_t)k * HW)[idx] = 0.f;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) (b.numbar + (size_t)q * HW)[idx] = 0.f;
+        return;
+    }
+
+    // genes at the cell: diffused (update) or as stored (read-only)
+    float pd[NP], rn[NP];
+    bool clip_ok[NP];
+    if (update) {
+        const Nbr nb = neighbours(gy, gx, H, W);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            const Diffused df = diffuse5(b.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
+            pd[q] = df.v;
+            const float inv = (df.n > 0) ? __builtin_amdgcn_rcpf((float)df.n) : 0.f;
+            const float qq = df.num * inv;
+            clip_ok[q] = (df.n > 0) && (qq >= 0.f) && (qq <= 1.f);
+            rn[q] = inv;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            pd[q] = (b.P + (size_t)q * HW)[idx];
+            clip_ok[q] = true;
+            rn[q] = 1.f;
+        }
+    }
+    float u[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) u[k] = (b.U + (size_t)k * HW)[idx];
+
+    // forward growth and pre-clip update (same arithmetic as the step kernel)
+    float sum[T::C];
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) sum[c] = 0.f;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) {
+        const float z = a[c] + dt * sum[c];
+        const float g1 = (b.gA1 + (size_t)c * HW)[idx];
+        zb[c] = (z >= 0.f && z <= 1.f) ? g1 : 0.f;
+        (b.gA + (size_t)c * HW)[idx] = zb[c];
+    }
+    // growth derivatives
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const float m = pd[k], s = pd[NK + k], h = pd[2 * NK + k];
+        const float d = u[k] - m;
+        const float e = growth_bell(d, s);
+        const float gb = dt * zb[T::dst[k]];
+        const float is2 = __builtin_amdgcn_rcpf(s * s);
+        const float common = 2.f * h * e * d * is2;           // dg/dm
+        (b.ubar + (size_t)k * HW)[idx] = -gb * common;        // dg/du = -dg/dm
+        const float dm = gb * common;
+        const float ds = gb * common * d * __builtin_amdgcn_rcpf(s);
+        const float dh = gb * (2.f * e - 1.f);
+        const float gpm = b.gP1 ? (b.gP1 + (size_t)k * HW)[idx] : 0.f;
+        const float gps = b.gP1 ? (b.gP1 + (size_t)(NK + k) * HW)[idx] : 0.f;
+        const float gph = b.gP1 ? (b.gP1 + (size_t)(2 * NK + k) * HW)[idx] : 0.f;
+        const float pb[3] = {gpm + dm, gps + ds, gph + dh};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const int q = p * NK + k;
+            if (update)
+                (b.numbar + (size_t)q * HW)[idx] = clip_ok[q] ? pb[p] * rn[q] : 0.f;
+            else
+                (b.gP + (size_t)q * HW)[idx] = pb[p];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2. tiled gather pass
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// Sum of one tap over both cells of the pair for NPL planes: v[p][q].
+template <int NPL, int PITCH, int CHS>
+__device__ __forceinline__ void tap_load_planes(float (&v)[NPL][2], const float* p)
+{
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) v[pl][q] = p[pl * CHS + q * PITCH];
+}
+
+template <int NPL, int PITCH, int CHS>
+__device__ __forceinline__ void quad_planes(float (&sum)[NPL][2], const float* p0, const float* p1,
+                                            const float* p2, const float* p3)
+{
+    float v0[NPL][2], v1[NPL][2], v2[NPL][2], v3[NPL][2];
+    tap_load_planes<NPL, PITCH, CHS>(v0, p0);
+    tap_load_planes<NPL, PITCH, CHS>(v1, p1);
+    tap_load_planes<NPL, PITCH, CHS>(v2, p2);
+    tap_load_planes<NPL, PITCH, CHS>(v3, p3);
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) sum[pl][q] = (v0[pl][q] + v1[pl][q]) + (v2[pl][q] + v3[pl][q]);
+}
+
+// One orbit: transpose-convolution FMAs for the KPS ubar planes, and the
+// per-wave beta products of the A plane (index KPS) with ubar at the cells.
+template <class T, int NPL, int NO, int NW>
+__device__ __forceinline__ void orbit_bwd(float (&g)[2], const float (&sum)[NPL][2],
+                                          const float (&uc)[T::KPS][2], cfloat* w, int t,
+                                          float (*og)[T::KPS][NO], int wave, int lane)
+{
+#pragma unroll
+    for (int j = 0; j < T::KPS; ++j) {
+        const float wj = w[j];
+        g[0] = fmaf(wj, sum[j][0], g[0]);
+        g[1] = fmaf(wj, sum[j][1], g[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < T::KPS; ++j) {
+        const float pr = wave_sum(fmaf(uc[j][1], sum[NPL - 1][1], uc[j][0] * sum[NPL - 1][0]));
+        if (lane == 0) og[wave][j][t] = pr;
+    }
+}
+
+template <class T, int R, int TY, int TX>
+__global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
+{
+    constexpr int NT = TY * TX / 2;
+    constexpr int NWV = NT / 64;
+    constexpr int KPS = T::KPS;
+    constexpr int NPL = KPS + 1;
+    constexpr int PY = TY + 2 * R;
+    constexpr int PITCH = tile_pitch<R, TX>();
+    constexpr int CHS = PY * PITCH;
+    constexpr int NO = Orbits<R>::N;
+    constexpr int WS = T::C * 8;
+    __shared__ float sm[NPL * CHS];
+    __shared__ float og[NWV][KPS][NO];
+
+    const int H = b.H, W = b.W;
+    const size_t HW = (size_t)H * W;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tyi = tile / b.tiles_x, txi = tile - tyi * b.tiles_x;
+    const int y0 = tyi * TY, x0 = txi * TX;
+    const int ly = 2 * (threadIdx.x / TX), lx = threadIdx.x % TX;
+    const int gy = y0 + ly, gx = x0 + lx;
+    const bool valid0 = (gy < H) && (gx < W);
+    const bool valid1 = (gy + 1 < H) && (gx < W);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const float* c = sm + (ly + R) * PITCH + (lx + R);
+
+    float gsum[2][T::C];
+#pragma unroll 1
+    for (int s = 0; s < T::C; ++s) {
+        const float* src[NPL];
+#pragma unroll
+        for (int j = 0; j < KPS; ++j) src[j] = b.ubar + (size_t)T::kidx[s][j] * HW;
+        src[KPS] = b.A + (size_t)s * HW;
+        __syncthreads();
+        stage_planes<NPL, R, TY, TX, NT, PITCH, CHS>(sm, src, H, W, y0, x0);
+        __syncthreads();
+        float uc[KPS][2];
+#pragma unroll
+        for (int j = 0; j < KPS; ++j) {
+            uc[j][0] = valid0 ? c[j * CHS] : 0.f;
+            uc[j][1] = valid1 ? c[j * CHS + PITCH] : 0.f;
+        }
+        float g[2] = {0.f, 0.f};
+        cfloat* w = (cfloat*)b.wt + s * 8;
+        int t = 0;
+#pragma unroll 1
+        for (int a = 1; a < R; ++a, w += WS, ++t) {
+            float sum[NPL][2];
+            quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
+            orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+        }
+#pragma unroll 1
+        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, ++t) {
+            float sum[NPL][2];
+            quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
+                                         c - a * PITCH + a, c - a * PITCH - a);
+            orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+        }
+#pragma unroll 1
+        for (int a = 2; a < R; ++a) {
+#pragma unroll 1
+            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, ++t) {
+                float s0[NPL][2], s1[NPL][2], sum[NPL][2];
+                quad_planes<NPL, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
+                                             c - a * PITCH + bb, c - a * PITCH - bb);
+                quad_planes<NPL, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
+                                             c - bb * PITCH + a, c - bb * PITCH - a);
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+                orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+            }
+        }
+        gsum[0][s] = g[0];
+        gsum[1][s] = g[1];
+        __syncthreads();
+        // shell-height partials of this tile: sum over waves, then over orbits
+        for (int e = threadIdx.x; e < KPS * 3; e += NT) {
+            const int j = e / 3, i = e - 3 * (e / 3);
+            const int k = T::kidx[s][j];
+            cfloat* bt = (cfloat*)b.bt + ((size_t)k * 3 + i) * NO;
+            float acc = 0.f;
+            for (int tt = 0; tt < NO; ++tt) {
+                float o = 0.f;
+#pragma unroll
+                for (int wv = 0; wv < NWV; ++wv) o += og[wv][j][tt];
+                acc = fmaf(o, bt[tt], acc);
+            }
+            b.part[((size_t)tile * T::NK + k) * 3 + i] = acc;
+        }
+    }
+
+    // direct term from the cell pass + convolution transpose
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (q == 0 ? !valid0 : !valid1) continue;
+        const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
+#pragma unroll
+        for (int s = 0; s < T::C; ++s) {
+            float* ga = b.gA + (size_t)s * HW;
+            ga[o] = ga[o] + gsum[q][s];
+        }
+    }
+    // transpose of the gene diffusion: gP(y) = sum over the disk of numbar(y + d);
+    // numbar vanishes wherever alpha does, so cells whose 5-neighbourhood has
+    // no alpha skip the reads
+    if (b.mode == MODE_LOCAL_UPDATE) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q == 0 ? !valid0 : !valid1) continue;
+            const Nbr nb = neighbours(gy + q, gx, H, W);
+            const bool any = b.alpha[nb.oc] | b.alpha[nb.ou] | b.alpha[nb.od] | b.alpha[nb.ol] |
+                             b.alpha[nb.orr];
+#pragma unroll
+            for (int pq = 0; pq < 3 * T::NK; ++pq) {
+                const float* nbp = b.numbar + (size_t)pq * HW;
+                float v = 0.f;
+                if (any) v = (((nbp[nb.ou] + nbp[nb.ol]) + nbp[nb.oc]) + nbp[nb.orr]) + nbp[nb.od];
+                (b.gP + (size_t)pq * HW)[nb.oc] = v;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. fixed-order reduction of the per-tile shell-height partials into gbeta
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void bwd_beta_reduce_kernel(const float* part, int n_tiles, int nk,
+                                                             const int* n_shells, float* gbeta)
+{
+    __shared__ float red[256];
+    const int e = blockIdx.x;           // (k, i)
+    const int k = e / 3, i = e - 3 * (e / 3);
+    float acc = 0.f;
+    for (int t = threadIdx.x; t < n_tiles; t += 256) acc += part[((size_t)t * nk + k) * 3 + i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int sft = 128; sft > 0; sft >>= 1) {
+        if (threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && i < n_shells[k]) gbeta[k * 3 + i] += red[0];
+}
+
+template <class T, int R, int TY, int TX>
+hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipStream_t s)
+{
+    const unsigned cells = (unsigned)a.H * (unsigned)a.W;
+    hipLaunchKernelGGL((bwd_cell_kernel<T>), dim3((cells + 255) / 256), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX>), dim3(a.n_tiles), dim3(TY * TX / 2), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bwd_beta_reduce_kernel, dim3(T::NK * 3), dim3(256), 0, s, a.part, a.n_tiles,
+                       T::NK, d_nshells, gbeta);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*bwd_launch_fn)(const BwdArgs&, const int*, float*, hipStream_t);
+
+constexpr int kBwdTY = 16, kBwdTX = 32;
+
+static bwd_launch_fn find_bwd(int table, int R)
+{
+    if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, kBwdTY, kBwdTX>;
+    if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, kBwdTY, kBwdTX>;
+    if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, kBwdTY, kBwdTX>;
+    if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, kBwdTY, kBwdTX>;
+    return nullptr;
+}
+
+}  // namespace lenia
 
 using namespace lenia;
 
@@ -10,7 +384,76 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
                                        const float* gP_next, float* gA_t, float* gP_t,
                                        float* gbeta, void* stream)
 {
-    (void)p; (void)A_t; (void)P_t; (void)saved; (void)gA_next; (void)gP_next;
-    (void)gA_t; (void)gP_t; (void)gbeta; (void)stream;
-    return set_error(LENIA_ERR_UNSUPPORTED, "adjoint not built yet");
+    try {
+        if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
+        if (p->batched) return set_error(LENIA_ERR_STATE, "adjoint needs a single-world plan");
+        WorldPlan& w = p->worlds[0];
+        if (w.mode == MODE_GLOBAL)
+            return set_error(LENIA_ERR_UNSUPPORTED, "adjoint needs localized genes");
+        bwd_launch_fn fn = find_bwd(p->table, p->R);
+        if (!fn) return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint kernel for this table / R");
+        if (!A_t || !P_t || !saved || !gA_next || !gA_t || !gP_t || !gbeta)
+            return set_error(LENIA_ERR_INVALID_ARG, "NULL argument (only gP_next may be NULL)");
+        const uintptr_t al = (uintptr_t)A_t | (uintptr_t)P_t | (uintptr_t)saved |
+                             (uintptr_t)gA_next | (uintptr_t)gA_t | (uintptr_t)gP_t |
+                             (uintptr_t)gbeta | (uintptr_t)gP_next;
+        if (al & 3) return set_error(LENIA_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+        const void* ins[] = {A_t, P_t, saved, gA_next, gP_next};
+        for (const void* q : ins)
+            if (q && (q == (const void*)gA_t || q == (const void*)gP_t))
+                return set_error(LENIA_ERR_INVALID_ARG, "gA_t / gP_t must not alias an input");
+        if ((const void*)gA_t == (const void*)gP_t)
+            return set_error(LENIA_ERR_INVALID_ARG, "gA_t and gP_t must differ");
+        hipStream_t s = (hipStream_t)stream;
+        const int tiles_x = (w.W + kBwdTX - 1) / kBwdTX;
+        const int n_tiles = tiles_x * ((w.H + kBwdTY - 1) / kBwdTY);
+        // workspaces, allocated on first use
+        if (!p->bw.ubar) {
+            void* q = nullptr;
+            if (hipMalloc(&q, w.NK * w.cells() * sizeof(float)) != hipSuccess)
+                return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
+            p->allocations.push_back(q);
+            p->ws_bytes += w.NK * w.cells() * sizeof(float);
+            p->bw.ubar = (float*)q;
+            if (w.mode == MODE_LOCAL_UPDATE) {
+                if (hipMalloc(&q, 3 * w.NK * w.cells() * sizeof(float)) != hipSuccess)
+                    return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
+                p->allocations.push_back(q);
+                p->ws_bytes += 3 * w.NK * w.cells() * sizeof(float);
+                p->bw.numbar = (float*)q;
+            }
+            if (hipMalloc(&q, (size_t)n_tiles * w.NK * 3 * sizeof(float)) != hipSuccess)
+                return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
+            p->allocations.push_back(q);
+            p->ws_bytes += (size_t)n_tiles * w.NK * 3 * sizeof(float);
+            p->bw.part = (float*)q;
+            p->bw.n_part = n_tiles;
+        }
+        BwdArgs a{};
+        a.A = A_t;
+        a.P = P_t;
+        a.U = (const float*)saved;
+        a.alpha = (const uint8_t*)saved + (size_t)w.NK * w.cells() * sizeof(float);
+        a.gA1 = gA_next;
+        a.gP1 = gP_next;
+        a.gA = gA_t;
+        a.gP = gP_t;
+        a.ubar = p->bw.ubar;
+        a.numbar = p->bw.numbar;
+        a.part = p->bw.part;
+        a.wt = w.d_wt;
+        a.bt = w.d_bt;
+        a.H = w.H;
+        a.W = w.W;
+        a.tiles_x = tiles_x;
+        a.n_tiles = n_tiles;
+        a.dt = (float)w.dt;
+        a.eps = eps_below(w.eps);
+        a.mode = w.mode;
+        hipError_t e = fn(a, w.d_nshells, gbeta, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+        return LENIA_OK;
+    } catch (...) {
+        return set_error(LENIA_ERR_STATE, "exception in lenia_backward");
+    }
 }

@@ -163,6 +163,26 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
                                        hipMemcpyHostToDevice, s);
         if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
     }
+    std::vector<float> hbt((size_t)w.NK * 3 * NO, 0.f);
+    for (int k = 0; k < w.NK; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int tt = 0; tt < NO; ++tt)
+                hbt[((size_t)k * 3 + i) * NO + tt] = hb[((size_t)k * 3 + i) * NO + korder[tt]];
+    if ((st = dmalloc(p, (void**)&w.d_bt, hbt.size() * sizeof(float))) != LENIA_OK) return st;
+    if ((st = dmalloc(p, (void**)&w.d_nshells, w.NK * sizeof(int))) != LENIA_OK) return st;
+    {
+        float* keep_bt = new float[hbt.size()];
+        std::memcpy(keep_bt, hbt.data(), hbt.size() * sizeof(float));
+        host_keep.push_back(keep_bt);
+        float* keep_ns = new float[w.NK];
+        std::memcpy(keep_ns, w.n_shells.data(), w.NK * sizeof(int));
+        host_keep.push_back(keep_ns);
+        hipError_t e1 = hipMemcpyAsync(w.d_bt, keep_bt, hbt.size() * sizeof(float),
+                                       hipMemcpyHostToDevice, s);
+        if (e1 == hipSuccess)
+            e1 = hipMemcpyAsync(w.d_nshells, keep_ns, w.NK * sizeof(int), hipMemcpyHostToDevice, s);
+        if (e1 != hipSuccess) return hip_fail(e1, "uploading kernel tables");
+    }
     if ((st = dmalloc(p, (void**)&w.d_w, hw.size() * sizeof(float))) != LENIA_OK) return st;
     if ((st = dmalloc(p, (void**)&w.d_bcoef, hb.size() * sizeof(float))) != LENIA_OK) return st;
     // host copies stay alive until the stream has consumed them

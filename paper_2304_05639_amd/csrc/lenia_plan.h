@@ -35,6 +35,8 @@ struct WorldPlan {
     float* d_w = nullptr;          // [NK][n_orbits] orbit weights of K~_k
     float* d_wt = nullptr;         // [n_orbits][C][8] by (orbit, source, slot)
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
+    float* d_bt = nullptr;         // the same in the step kernel's orbit order
+    int* d_nshells = nullptr;      // [NK]
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
     float* ws_P = nullptr;         // [3][NK][H][W] (gene update only)
     size_t cells() const { return (size_t)H * W; }

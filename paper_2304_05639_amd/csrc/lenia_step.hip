@@ -14,6 +14,7 @@
 // Output goes to buffers distinct from the inputs (the host ping-pongs).
 #include <utility>
 
+#include "lenia_device.h"
 #include "lenia_internal.h"
 
 namespace lenia {
@@ -22,22 +23,10 @@ namespace lenia {
 #define LENIA_MIN_WAVES 2   // minimum waves per SIMD the register budget must allow
 #endif
 
-// Block id -> tile id such that consecutive tiles land on the same XCD (the
-// dispatcher deals workgroups round-robin over the 8 XCDs, each with its own
-// L2): XCD x receives a contiguous band of tile rows, so halo re-reads of
-// neighbouring tiles hit that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int nb)
-{
-    const int q = nb >> 3, r = nb & 7;
-    const int xcd = bid & 7, slot = bid >> 3;
-    return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-}
 
 // Kernel weights, per orbit t and source channel s: wt[(t * C + s) * 8 + j] is
-// the weight of the j-th kernel reading channel s (slot order of the table),
-// read through the constant address space: the index is uniform, so these
-// are scalar loads feeding the FMAs as SGPR operands.
-typedef const __attribute__((address_space(4))) float cfloat;
+// the weight of the j-th kernel reading channel s (slot order of the table);
+// the index is uniform, so these are scalar loads.
 
 // Potentials of a vertical pair of cells (c and c + PITCH):
 //   u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
@@ -153,17 +142,7 @@ __device__ __forceinline__ void conv_pair(const float* c, cfloat* __restrict__ w
             for (int j = 0; j < T::KPS; ++j) u[q][T::kidx[s][j]] = acc[q][s][j];
 }
 
-// G(u; m, s, h) = h (2 exp(-(u-m)^2 / (2 s^2)) - 1), with the hardware
-// reciprocal and exponential (a few ulp; the exponent's error only matters
-// where the exponential is far below the state tolerance).
-__device__ __forceinline__ float growth(float u, float m, float s, float h)
-{
-    const float d = u - m;
-    const float inv = __builtin_amdgcn_rcpf(2.f * s * s);
-    return h * (2.f * __expf(-(d * d) * inv) - 1.f);
-}
 
-__device__ __forceinline__ float clip01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
 
 // Gene diffusion, alpha mask, growth and update of one cell (gy, gx) given its
 // potentials u and its current state a[c]; writes A' and P' (and the saved
@@ -193,21 +172,13 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
         float pd[NP];
         if (alpha) {
             // diffusion of every gene plane over the r = 1 disk
-            const int ym = (gy == 0) ? H - 1 : gy - 1;
-            const int yp = (gy == H - 1) ? 0 : gy + 1;
-            const int xm = (gx == 0) ? W - 1 : gx - 1;
-            const int xp = (gx == W - 1) ? 0 : gx + 1;
-            const uint32_t ou = (uint32_t)ym * W + gx, od = (uint32_t)yp * W + gx;
-            const uint32_t ol = (uint32_t)gy * W + xm, orr = (uint32_t)gy * W + xp;
+            const Nbr nb = neighbours(gy, gx, H, W);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const float* pl = wd.P + (size_t)q * HW;
-                const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
-                const float num = (((vu + vl) + vc) + vr) + vd;
-                const int n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
-                const float v = (n > 0) ? clip01(num * __builtin_amdgcn_rcpf((float)n)) : 0.f;
-                pd[q] = v;
-                alpha = alpha && (v > eps);
+                const Diffused df =
+                    diffuse5(wd.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
+                pd[q] = df.v;
+                alpha = alpha && (df.v > eps);
             }
         }
         if (alpha) {
@@ -240,10 +211,6 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 template <int TY, int TX>
 constexpr int step_threads() { return TY * TX / 2; }
 
-// LDS row pitch of a staged tile: tile width + halo, rounded up to a multiple
-// of 64 floats so that every channel / row offset is a ds_read2st64 offset.
-template <int R, int TX>
-constexpr int tile_pitch() { return ((TX + 2 * R + 63) / 64) * 64; }
 
 template <class T, int R, int TY, int TX>
 constexpr int tile_lds_floats() { return T::C * (TY + 2 * R) * tile_pitch<R, TX>(); }
