@@ -22,13 +22,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = 384        # read A 12 + write A 12 + read P 180 + write P 180 (FP32)
-STEP_SRC = os.path.join(ROOT, "paper_2304_05639_amd", "csrc", "lenia_step.hip")
+STEP_SRCS = [os.path.join(ROOT, "paper_2304_05639_amd", "csrc", f)
+             for f in ("lenia_step.hip", "lenia_device.h", "lenia_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_4096.json")
 
 
 def kernel_sha() -> str:
-    with open(STEP_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the step kernel's sources (counters are only valid for them)."""
+    h = hashlib.sha256()
+    for fn in STEP_SRCS:
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(cells: int):
@@ -69,6 +74,64 @@ def cpu_baseline(world, budget_s: float = 12.0):
                       f"convolution, OpenMP over rows), {dt:.1f} s"}
 
 
+def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3):
+    """256^2 differentiable rollout (T = 64, checkpoint every 8, MSE to a
+    random target): time of the backward pass (recomputing each segment with
+    saved potentials, then the adjoint) over the forward pass (with checkpoint
+    saves), median of `reps`."""
+    import torch
+    from paper_2304_05639_amd import inputs, lenia
+    from paper_2304_05639_amd.autograd import rollout
+    w = inputs.config5()
+    plan = lenia.Plan(w)
+    A0 = torch.tensor(w.A, device="cuda", requires_grad=True)
+    P0 = torch.tensor(w.P, device="cuda", requires_grad=True)
+    beta = torch.tensor(w.beta, dtype=torch.float32, device="cuda", requires_grad=True)
+    target = torch.tensor(w.target, device="cuda")
+    fw, bw = [], []
+    for _ in range(reps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record()
+        AT, _ = rollout(A0, P0, beta, plan, steps_T, ckpt)
+        loss = ((AT - target) ** 2).mean()
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        fw.append(e0.elapsed_time(e1))
+        bw.append(e1.elapsed_time(e2))
+        A0.grad = P0.grad = beta.grad = None
+    fw, bw = sorted(fw[1:]), sorted(bw[1:])
+    f, b = fw[len(fw) // 2], bw[len(bw) // 2]
+    return {"value": b / f, "forward_ms": f, "backward_ms": b,
+            "workload": "256x256, 3 channels, 15 kernels, T=64, checkpoint every 8, MSE loss"}
+
+
+def batched_throughput(steps: int = 20, warmup: int = 2):
+    """256 independent worlds of sides 128..1024 stepped together in one
+    persistent launch per step (graph replay): cell-updates/s over all worlds."""
+    import torch
+    from paper_2304_05639_amd import inputs, lenia
+    worlds = inputs.config4()
+    cells = sum(w.H * w.W for w in worlds)
+    bp = lenia.BatchedPlan(worlds)
+    As = [torch.tensor(w.A, device="cuda") for w in worlds]
+    Ps = [torch.tensor(w.P, device="cuda") for w in worlds]
+    bp.step(As, Ps, n_steps=warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    bp.step(As, Ps, n_steps=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = bp.info()
+    return {"value": cells / (ms / 1e3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "cells": cells, "worlds": len(worlds), "tile": [info.tile_y, info.tile_x],
+            "roofline_frac_algorithmic": BYTES_PER_CELL * cells / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +139,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a 1 GiB fill, copy and sum (reference kernels for the "
+                         "HBM byte counters)")
+    ap.add_argument("--batched", action="store_true",
+                    help="also time the 256-world batched workload (slow input generation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
@@ -137,7 +206,18 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
     }
-    del A2, P2
+    del A2, P2, A, P
+    if args.calibrate:
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        out["calibration_sum"] = float(src.sum())
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_backward:
+        out["bwd_fwd_ratio"] = backward_forward_ratio()
+    if args.batched:
+        out["batched"] = batched_throughput()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(world)
     print(json.dumps(out), flush=True)

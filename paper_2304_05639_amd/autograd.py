@@ -50,6 +50,9 @@ class LeniaRollout(torch.autograd.Function):
         gP = torch.zeros_like(ckpts[0][1]) if gP is None else gP.contiguous()
         gbeta = torch.zeros(plan.NK, 3, dtype=torch.float32, device=A_ref.device)
         saved = [plan.new_saved() for _ in range(max(ctx.steps))]
+        # two cotangent buffers, used alternately (an output must not alias an input)
+        bufs = [(torch.empty_like(gA), torch.empty_like(gP)) for _ in range(2)]
+        nb = 0
         for seg in reversed(range(len(ctx.steps))):
             A, P = ckpts[seg]
             states = [(A, P)]
@@ -57,8 +60,10 @@ class LeniaRollout(torch.autograd.Function):
                 A, P = plan.step(A, P, saved=saved[i])
                 states.append((A, P))
             for i in reversed(range(ctx.steps[seg])):
+                oA, oP = bufs[nb]
+                nb ^= 1
                 gA, gP, _ = plan.backward(states[i][0], states[i][1], saved[i], gA, gP,
-                                          gbeta=gbeta)
+                                          gA_t=oA, gP_t=oP, gbeta=gbeta)
         return gA, gP, gbeta.to(ctx.saved_tensors[0].dtype), None, None, None
 
 

@@ -13,7 +13,7 @@
 //   numbar   = Pbar_d [n > 0 and 0 <= num/n <= 1] / n
 //   gA_c    += sum_{src(k)=c} K~_k (x) ubar_k  (K~ even: correlation again)
 //   gP(y)    = sum over the r = 1 disk of numbar(y + d)
-//   dL/dbeta_{k,i} = sum_t G_k(t) bcoef_{k,i}(t),  G_k(t) = <ubar_k, orbit-sum_t A_src>
+//   dL/dbeta_{k,i} = < ubar_k, sum_t bcoef_{k,i}(t) orbit-sum_t A_src >
 // Three kernels: a per-cell pass, a tiled gather pass (convolution transpose,
 // diffusion transpose, shell-height partials per tile), and a fixed-order
 // reduction of the partials.  No float atomics: results are deterministic.
@@ -39,7 +39,8 @@ struct BwdArgs {
     float* numbar;           // workspace [3NK][H][W] (gene update only)
     float* part;             // workspace [n_tiles][NK][3]
     const float* wt;         // orbit weights [NO][C][8] in the step kernel's orbit order
-    const float* bt;         // beta coefficients [NK][3][NO] in the same orbit order
+    const float* bt;         // shell-height coefficients [NO][C][16] (slot j, shell i at
+                             // j * 3 + i) in the same orbit order
     int H, W, tiles_x, n_tiles;
     float dt, eps;
     int mode;
@@ -181,12 +182,12 @@ __device__ __forceinline__ void quad_planes(float (&sum)[NPL][2], const float* p
         for (int q = 0; q < 2; ++q) sum[pl][q] = (v0[pl][q] + v1[pl][q]) + (v2[pl][q] + v3[pl][q]);
 }
 
-// One orbit: transpose-convolution FMAs for the KPS ubar planes, and the
-// per-wave beta products of the A plane (index KPS) with ubar at the cells.
-template <class T, int NPL, int NO, int NW>
-__device__ __forceinline__ void orbit_bwd(float (&g)[2], const float (&sum)[NPL][2],
-                                          const float (&uc)[T::KPS][2], cfloat* w, int t,
-                                          float (*og)[T::KPS][NO], int wave, int lane)
+// One orbit: transpose-convolution FMAs for the KPS ubar planes (weights w),
+// and the shell-height coefficient FMAs on the A plane (index KPS):
+// v[q][j][i] += bcoef_{k_j, i}(t) * (orbit sum of A at cell q).
+template <class T, int NPL>
+__device__ __forceinline__ void orbit_bwd(float (&g)[2], float (&v)[2][T::KPS][3],
+                                          const float (&sum)[NPL][2], cfloat* w, cfloat* bc)
 {
 #pragma unroll
     for (int j = 0; j < T::KPS; ++j) {
@@ -195,10 +196,13 @@ __device__ __forceinline__ void orbit_bwd(float (&g)[2], const float (&sum)[NPL]
         g[1] = fmaf(wj, sum[j][1], g[1]);
     }
 #pragma unroll
-    for (int j = 0; j < T::KPS; ++j) {
-        const float pr = wave_sum(fmaf(uc[j][1], sum[NPL - 1][1], uc[j][0] * sum[NPL - 1][0]));
-        if (lane == 0) og[wave][j][t] = pr;
-    }
+    for (int j = 0; j < T::KPS; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float c = bc[j * 3 + i];
+            v[0][j][i] = fmaf(c, sum[NPL - 1][0], v[0][j][i]);
+            v[1][j][i] = fmaf(c, sum[NPL - 1][1], v[1][j][i]);
+        }
 }
 
 template <class T, int R, int TY, int TX>
@@ -211,10 +215,10 @@ __global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
     constexpr int PY = TY + 2 * R;
     constexpr int PITCH = tile_pitch<R, TX>();
     constexpr int CHS = PY * PITCH;
-    constexpr int NO = Orbits<R>::N;
-    constexpr int WS = T::C * 8;
+    constexpr int WS = T::C * 8;     // weights per orbit
+    constexpr int BS = T::C * 16;    // shell-height coefficients per orbit
     __shared__ float sm[NPL * CHS];
-    __shared__ float og[NWV][KPS][NO];
+    __shared__ float red[NWV][KPS * 3];
 
     const int H = b.H, W = b.W;
     const size_t HW = (size_t)H * W;
@@ -226,6 +230,7 @@ __global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
     const bool valid0 = (gy < H) && (gx < W);
     const bool valid1 = (gy + 1 < H) && (gx < W);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    (void)lane;
     const float* c = sm + (ly + R) * PITCH + (lx + R);
 
     float gsum[2][T::C];
@@ -245,25 +250,32 @@ __global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
             uc[j][1] = valid1 ? c[j * CHS + PITCH] : 0.f;
         }
         float g[2] = {0.f, 0.f};
+        float v[2][KPS][3];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int j = 0; j < KPS; ++j)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) v[q][j][i] = 0.f;
         cfloat* w = (cfloat*)b.wt + s * 8;
-        int t = 0;
+        cfloat* bc = (cfloat*)b.bt + s * 16;
 #pragma unroll 1
-        for (int a = 1; a < R; ++a, w += WS, ++t) {
+        for (int a = 1; a < R; ++a, w += WS, bc += BS) {
             float sum[NPL][2];
             quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-            orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+            orbit_bwd<T, NPL>(g, v, sum, w, bc);
         }
 #pragma unroll 1
-        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, ++t) {
+        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
             float sum[NPL][2];
             quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
                                          c - a * PITCH + a, c - a * PITCH - a);
-            orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+            orbit_bwd<T, NPL>(g, v, sum, w, bc);
         }
 #pragma unroll 1
         for (int a = 2; a < R; ++a) {
 #pragma unroll 1
-            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, ++t) {
+            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
                 float s0[NPL][2], s1[NPL][2], sum[NPL][2];
                 quad_planes<NPL, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
                                              c - a * PITCH + bb, c - a * PITCH - bb);
@@ -273,25 +285,27 @@ __global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
                 for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
                     for (int q = 0; q < 2; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
-                orbit_bwd<T, NPL, NO, NWV>(g, sum, uc, w, t, og, wave, lane);
+                orbit_bwd<T, NPL>(g, v, sum, w, bc);
             }
         }
         gsum[0][s] = g[0];
         gsum[1][s] = g[1];
-        __syncthreads();
-        // shell-height partials of this tile: sum over waves, then over orbits
-        for (int e = threadIdx.x; e < KPS * 3; e += NT) {
-            const int j = e / 3, i = e - 3 * (e / 3);
-            const int k = T::kidx[s][j];
-            cfloat* bt = (cfloat*)b.bt + ((size_t)k * 3 + i) * NO;
-            float acc = 0.f;
-            for (int tt = 0; tt < NO; ++tt) {
-                float o = 0.f;
+        // shell-height partials of this tile: ubar at the cell times its
+        // coefficient-weighted orbit sums, reduced over the block in a fixed order
 #pragma unroll
-                for (int wv = 0; wv < NWV; ++wv) o += og[wv][j][tt];
-                acc = fmaf(o, bt[tt], acc);
+        for (int j = 0; j < KPS; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float pr = wave_sum(fmaf(uc[j][1], v[1][j][i], uc[j][0] * v[0][j][i]));
+                if (lane == 0) red[wave][j * 3 + i] = pr;
             }
-            b.part[((size_t)tile * T::NK + k) * 3 + i] = acc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < KPS * 3; e += NT) {
+            float acc = 0.f;
+#pragma unroll
+            for (int wv = 0; wv < NWV; ++wv) acc += red[wv][e];
+            const int k = T::kidx[s][e / 3];
+            b.part[((size_t)tile * T::NK + k) * 3 + (e % 3)] = acc;
         }
     }
 
@@ -364,14 +378,21 @@ hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipS
 
 typedef hipError_t (*bwd_launch_fn)(const BwdArgs&, const int*, float*, hipStream_t);
 
-constexpr int kBwdTY = 16, kBwdTX = 32;
-
-static bwd_launch_fn find_bwd(int table, int R)
+// Gather-pass tile: 16 x 32 cells, or 8 x 32 when that leaves too few tiles to
+// fill the device.
+static bwd_launch_fn find_bwd(int table, int R, bool small)
 {
-    if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, kBwdTY, kBwdTX>;
-    if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, kBwdTY, kBwdTX>;
-    if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, kBwdTY, kBwdTX>;
-    if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, kBwdTY, kBwdTX>;
+    if (!small) {
+        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 16, 32>;
+        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 16, 32>;
+        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 16, 32>;
+        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 16, 32>;
+    } else {
+        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 8, 32>;
+        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 8, 32>;
+        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 8, 32>;
+        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 8, 32>;
+    }
     return nullptr;
 }
 
@@ -390,7 +411,9 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
         WorldPlan& w = p->worlds[0];
         if (w.mode == MODE_GLOBAL)
             return set_error(LENIA_ERR_UNSUPPORTED, "adjoint needs localized genes");
-        bwd_launch_fn fn = find_bwd(p->table, p->R);
+        const bool small = ((size_t)((w.H + 15) / 16) * ((w.W + 31) / 32) < 1024);
+        const int kBwdTY = small ? 8 : 16, kBwdTX = 32;
+        bwd_launch_fn fn = find_bwd(p->table, p->R, small);
         if (!fn) return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint kernel for this table / R");
         if (!A_t || !P_t || !saved || !gA_next || !gA_t || !gP_t || !gbeta)
             return set_error(LENIA_ERR_INVALID_ARG, "NULL argument (only gP_next may be NULL)");
@@ -422,12 +445,14 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
                 p->ws_bytes += 3 * w.NK * w.cells() * sizeof(float);
                 p->bw.numbar = (float*)q;
             }
-            if (hipMalloc(&q, (size_t)n_tiles * w.NK * 3 * sizeof(float)) != hipSuccess)
+            // sized for the larger tile count of the two gather tiles
+            const size_t max_tiles = (size_t)((w.W + 31) / 32) * ((w.H + 7) / 8);
+            if (hipMalloc(&q, max_tiles * w.NK * 3 * sizeof(float)) != hipSuccess)
                 return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
             p->allocations.push_back(q);
-            p->ws_bytes += (size_t)n_tiles * w.NK * 3 * sizeof(float);
+            p->ws_bytes += max_tiles * w.NK * 3 * sizeof(float);
             p->bw.part = (float*)q;
-            p->bw.n_part = n_tiles;
+            p->bw.n_part = (int)max_tiles;
         }
         BwdArgs a{};
         a.A = A_t;

@@ -71,6 +71,8 @@ static void free_all(lenia_plan_t p)
 {
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     p->graph = nullptr;
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    p->capture_stream = nullptr;
     for (void* q : p->allocations) (void)hipFree(q);
     p->allocations.clear();
 }
@@ -163,11 +165,17 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
                                        hipMemcpyHostToDevice, s);
         if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
     }
-    std::vector<float> hbt((size_t)w.NK * 3 * NO, 0.f);
-    for (int k = 0; k < w.NK; ++k)
-        for (int i = 0; i < 3; ++i)
-            for (int tt = 0; tt < NO; ++tt)
-                hbt[((size_t)k * 3 + i) * NO + tt] = hb[((size_t)k * 3 + i) * NO + korder[tt]];
+    // shell-height coefficients in the same orbit order: [orbit][source][16],
+    // slot j and shell i at j * 3 + i
+    std::vector<float> hbt((size_t)NO * w.C * 16, 0.f);
+    for (int tt = 0; tt < NO; ++tt)
+        for (int sc = 0; sc < w.C; ++sc)
+            for (int j = 0; j < kps; ++j) {
+                const int k = (p->table == TABLE_3x15) ? Table3x15::kidx[sc][j] : Table1x1::kidx[sc][j];
+                for (int i = 0; i < 3; ++i)
+                    hbt[((size_t)tt * w.C + sc) * 16 + j * 3 + i] =
+                        hb[((size_t)k * 3 + i) * NO + korder[tt]];
+            }
     if ((st = dmalloc(p, (void**)&w.d_bt, hbt.size() * sizeof(float))) != LENIA_OK) return st;
     if ((st = dmalloc(p, (void**)&w.d_nshells, w.NK * sizeof(int))) != LENIA_OK) return st;
     {
@@ -369,15 +377,25 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
     return LENIA_OK;
 }
 
+// 16 x 32 cells, or 8 x 32 when the worlds have too few such tiles to keep
+// every CU busy (about 4 workgroups per CU).
 static void default_tile(lenia_plan_t p)
 {
     int tys[16], txs[16];
     const int nc = std::min(16, step_tile_candidates(p->table, p->R, tys, txs, 16));
+    size_t tiles16 = 0;
+    for (const WorldPlan& w : p->worlds) tiles16 += (size_t)tiles_of(w.H, 16) * tiles_of(w.W, 32);
+    const int want_y = (tiles16 < 1024) ? 8 : 16;
     p->tile_y = tys[0];
     p->tile_x = txs[0];
     for (int i = 0; i < nc; ++i)
         if (tys[i] == 16 && txs[i] == 32) {
             p->tile_y = 16;
+            p->tile_x = 32;
+        }
+    for (int i = 0; i < nc; ++i)
+        if (tys[i] == want_y && txs[i] == 32) {
+            p->tile_y = want_y;
             p->tile_x = 32;
         }
 }
@@ -458,6 +476,8 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     }
     if (st == LENIA_OK) st = finish_tile_choice(p, &ds[0], s);
     if (st == LENIA_OK && batched) {
+        // persistent grid: as many workgroups as fit on the device at once
+        p->grid = batch_blocks_per_cu(p->table, p->R, p->tile_y, p->tile_x) * device_cus(p->device);
         std::vector<int2> items;
         for (int i = 0; i < n; ++i) {
             const WorldPlan& w = p->worlds[i];
@@ -697,7 +717,7 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
         std::vector<float*> va(A, A + n), vp(n, nullptr);
         if (P) vp.assign(P, P + n);
         hipError_t e = hipSuccess;
-        const bool same = (va == p->graph_A && vp == p->graph_P && p->graph && p->graph_stream == s);
+        const bool same = (va == p->graph_A && vp == p->graph_P && p->graph);
         if (!same) {
             lenia_status st = fill_batch_tables(p, A, P ? P : vp.data(), s);
             if (st != LENIA_OK) return st;
@@ -705,15 +725,22 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
                 (void)hipGraphExecDestroy(p->graph);
                 p->graph = nullptr;
             }
-            // capture the two-phase pair
+            // capture the two-phase pair on the plan's private stream (the
+            // caller's stream may be the legacy null stream, which cannot be
+            // captured); the graph is then launched into the caller's stream
+            if (!p->capture_stream) {
+                e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_fail(e, "creating the capture stream");
+            }
+            hipStream_t cs = p->capture_stream;
             hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
                 BatchList b0{p->d_tables[0], p->d_items, p->n_items};
                 BatchList b1{p->d_tables[1], p->d_items, p->n_items};
-                hipError_t le = p->batch_fn(b0, p->mode, p->grid, s);
-                if (le == hipSuccess) le = p->batch_fn(b1, p->mode, p->grid, s);
-                e = hipStreamEndCapture(s, &g);
+                hipError_t le = p->batch_fn(b0, p->mode, p->grid, cs);
+                if (le == hipSuccess) le = p->batch_fn(b1, p->mode, p->grid, cs);
+                e = hipStreamEndCapture(cs, &g);
                 if (e == hipSuccess) e = le;
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
@@ -724,7 +751,6 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
             }
             p->graph_A = va;
             p->graph_P = vp;
-            p->graph_stream = s;
         }
         for (int i = 0; i + 1 < n_steps && e == hipSuccess; i += 2) e = hipGraphLaunch(p->graph, s);
         if (e == hipSuccess && (n_steps % 2 == 1)) {

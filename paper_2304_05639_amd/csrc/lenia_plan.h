@@ -69,7 +69,7 @@ struct lenia_plan_ {
     int n_items = 0, grid = 0;
     std::vector<float*> graph_A, graph_P;                 // pointer set of the graph
     hipGraphExec_t graph = nullptr;
-    hipStream_t graph_stream = nullptr;
+    hipStream_t capture_stream = nullptr;                 // private stream used for capture
     // adjoint
     lenia::BackwardWs bw;
     std::vector<void*> allocations;

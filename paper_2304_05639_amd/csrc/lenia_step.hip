@@ -327,14 +327,27 @@ hipError_t launch_batch(const BatchList& b, int mode, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
+// Workgroups of the persistent kernel that fit on one CU at once.
+template <class T, int R, int TY, int TX>
+int batch_occupancy()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batch_kernel<T, R, TY, TX>,
+                                                     TY * TX / 2, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+
 struct Entry {
     int table, R, ty, tx;
     step_launch_fn step;
     batch_launch_fn batch;
+    int (*occupancy)();
 };
 
-#define LENIA_ENTRY(TB, TID, RR, TYY, TXX) \
-    {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>}
+#define LENIA_ENTRY(TB, TID, RR, TYY, TXX)                                                   \
+    {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>, \
+     &batch_occupancy<TB, RR, TYY, TXX>}
 
 static const Entry kEntries[] = {
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 32),
@@ -343,9 +356,11 @@ static const Entry kEntries[] = {
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 64),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 64),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 16, 32),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 8, 32),
     LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 32),
-    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 64),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 8, 32),
     LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 16, 32),
+    LENIA_ENTRY(Table1x1, TABLE_1x1, 12, 8, 32),
 };
 
 step_launch_fn find_step_launcher(int table, int R, int ty, int tx)
@@ -360,6 +375,13 @@ batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx)
     for (const Entry& e : kEntries)
         if (e.table == table && e.R == R && e.ty == ty && e.tx == tx) return e.batch;
     return nullptr;
+}
+
+int batch_blocks_per_cu(int table, int R, int ty, int tx)
+{
+    for (const Entry& e : kEntries)
+        if (e.table == table && e.R == R && e.ty == ty && e.tx == tx) return e.occupancy();
+    return 1;
 }
 
 int step_tile_candidates(int table, int R, int* ty, int* tx, int max)
