@@ -132,6 +132,51 @@ def batched_throughput(steps: int = 20, warmup: int = 2):
             "roofline_frac_algorithmic": BYTES_PER_CELL * cells / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
+# MFMA instructions (v_mfma_f32_16x16x32_bf16, 16384 flops each) per tile of
+# the DFT form: forward transforms 3 channels x (192 + 384), inverse 15 kernels
+# x (240 + 108); every product is issued three times (hi*hi, hi*lo, lo*hi).
+DFT_MFMA_PER_TILE = 3 * (192 + 384) + 15 * (240 + 108)
+MFMA_FLOPS = 16 * 16 * 32 * 2
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def dft_form(world, steps: int = 20, warmup: int = 2):
+    """The split-bf16 DFT-as-GEMM form on the same world: full-step throughput,
+    and the MFMA kernel alone (lenia_potentials) against the dense bf16 peak."""
+    import torch
+    from paper_2304_05639_amd import lenia
+    plan = lenia.Plan(world, conv=lenia.CONV_DFT_SPLIT_BF16)
+    V = plan.info().tile_y
+    n_tiles = -(-world.H // V) * -(-world.W // V)
+    A = torch.tensor(world.A, device="cuda")
+    P = torch.tensor(world.P, device="cuda")
+    U = torch.empty(world.n_kernels, world.H, world.W, device="cuda")
+    for _ in range(warmup):
+        plan.potentials(A, U)
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.potentials(A, U)
+    e1.record()
+    A2, P2 = torch.empty_like(A), torch.empty_like(P)
+    plan.step(A, P, A2, P2, n_steps=warmup)
+    e2.record()
+    plan.step(A2, P2, A, P, n_steps=steps)
+    e3.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / steps
+    s_ms = e2.elapsed_time(e3) / steps
+    flops = n_tiles * DFT_MFMA_PER_TILE * MFMA_FLOPS
+    achieved = flops / (k_ms / 1e3) / 1e12
+    return {"value": world.H * world.W / (s_ms / 1e3), "unit": "cell-updates/s",
+            "ms_per_step": s_ms, "mfma_kernel_ms": k_ms,
+            "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
+                         "traffic": None},
+            "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +184,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=str, default="")
+    ap.add_argument("--conv", choices=["direct", "dft"], default="direct",
+                    help="potential form of the timed step: direct FP32 (default) or the "
+                         "split-bf16 DFT-as-GEMM form on MFMA")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-dft", action="store_true", help="skip the MFMA DFT-form leg")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB fill, copy and sum (reference kernels for the "
                          "HBM byte counters)")
@@ -158,7 +207,8 @@ def main():
     world = inputs.config3()
     cells = world.H * world.W
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
-    plan = lenia.Plan(world, tile=tile)
+    conv = lenia.CONV_DFT_SPLIT_BF16 if args.conv == "dft" else lenia.CONV_AUTO
+    plan = lenia.Plan(world, tile=tile, conv=conv)
     info = plan.info()
     dev = torch.device("cuda", 0)
     A = torch.tensor(world.A, device=dev)
@@ -200,13 +250,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lenia-3ch15k-4096x4096-localized-genes-2000-blobs",
                    "world": [world.H, world.W], "channels": 3, "kernels": 15, "R": world.R,
-                   "dt": world.dt, "tile": [info.tile_y, info.tile_x], "conv": "direct_f32",
+                   "dt": world.dt, "tile": [info.tile_y, info.tile_x],
+                   "conv": "dft_split_bf16" if args.conv == "dft" else "direct_f32",
                    "wall_s": wall},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
     }
     del A2, P2, A, P
+    if not args.no_dft and args.conv == "direct":
+        out["dft_split_bf16"] = dft_form(world)
     if args.calibrate:
         src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

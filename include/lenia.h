@@ -152,6 +152,12 @@ LENIA_API lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float
 LENIA_API lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P,
                                 int32_t n_steps, void* stream);
 
+/* The potentials u_k = K~_k * A_src(k) (Section 2.1's normalized kernels;
+ * the "potential" of Section 2.2) of the state A of a single-world plan, with
+ * the plan's convolution form, into U float[NK][H][W] (device, not aliasing
+ * A).  No gene or state update. */
+LENIA_API lenia_status lenia_potentials(lenia_plan_t p, const float* A, float* U, void* stream);
+
 /* Bytes of the `saved` buffer of lenia_step / lenia_backward. */
 LENIA_API size_t lenia_saved_bytes(lenia_plan_t p);
 

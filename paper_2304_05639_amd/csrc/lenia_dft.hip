@@ -1,0 +1,485 @@
+// Potentials by tile-local DFT as matrix products on the MFMA units (gfx950).
+//
+// u_k = K~_k * A_src(k) is a circular convolution; on a 64 x 64 window of A
+// (the 40 x 40 output tile plus an R-cell halo, R = 12) it equals the inverse
+// DFT of DFT(window) times the kernel's DFT (Section 2.1 computes the
+// convolution through the convolution theorem).  The kernel is even, so its
+// DFT is real.  With C[f][i] = cos(2 pi f i / 64), S[f][i] = sin(2 pi f i / 64)
+// and real-embedded complex matrices, per tile:
+//   GEMM1  [Y_re | Y_im]     (64 x 128) = X (64 x 64) [C | -S]            per channel
+//   GEMM2  [Xh_re; Xh_im]    (128 x 64) = [[C, S], [-S, C]] [Y_re; Y_im]  per channel
+//          U = Xh * Khat_k (real, 1/64^2 folded in)                        per kernel
+//   GEMM3  [Z_re; Z_im]^T    (64 x 2V)  = [U_re; U_im]^T [[C_V, -S_V], [S_V, C_V]]^T
+//   GEMM4  u_k               (V x V)    = [Z_re | Z_im] [C'_V; -S'_V]
+// where C_V / S_V keep the V output rows (columns) of the inverse transform.
+// Every GEMM runs in bf16 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
+// each operand x is split as hi = bf16(x), lo = bf16(x - hi) and a product is
+// hi*hi + hi*lo + lo*hi (about 16 significant bits).  The DFT matrices are
+// built in FP64 on the host and split there; data operands are split here.
+//
+// MFMA operand layouts (16x16x32): lane l holds A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16] for j < 8; the 16 x 16 FP32 result has
+// D[4 (l / 16) + j][l % 16] in lane l, j < 4.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "lenia.h"
+#include "lenia_device.h"
+#include "lenia_internal.h"
+#include "lenia_plan.h"
+
+namespace lenia {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int DT = 64;                   // DFT tile
+constexpr int DT2 = 128;                 // real-embedded complex dimension
+constexpr int XS_P = DT + 8;             // LDS row pitches (bf16 / fp32 elements)
+constexpr int YT_P = DT2 + 8;
+constexpr int XH_P = DT2 + 4;
+constexpr int ZC_P = DT2 + 8;
+constexpr int ZC_ROWS = 48;
+
+struct DftTables {
+    const __bf16* f1t;    // [2][128][64]  hi, lo of [C | -S]^T
+    const __bf16* f2;     // [2][128][128] hi, lo of [[C, S], [-S, C]]
+    const __bf16* f3;     // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
+    const __bf16* f4t;    // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
+    const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2
+};
+
+struct DftArgs {
+    const float* A;       // [C][H][W]
+    float* U;             // [NK][H][W] potentials (output)
+    DftTables t;
+    int H, W, tiles_x, n_tiles;
+};
+
+__device__ __forceinline__ f32x4 mma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                      const bf16x8& bl, f32x4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    return c;
+}
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo)
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const __bf16 h = (__bf16)x[j];
+        hi[j] = h;
+        lo[j] = (__bf16)(x[j] - (float)h);
+    }
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *(const bf16x8*)p; }
+
+// Writes 4 consecutive values (split) as bf16 hi / lo.
+__device__ __forceinline__ void st4_split(__bf16* hi, __bf16* lo, const f32x4& v)
+{
+    bf16x4 h, l;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const __bf16 b = (__bf16)v[j];
+        h[j] = b;
+        l[j] = (__bf16)(v[j] - (float)b);
+    }
+    *(bf16x4*)hi = h;
+    *(bf16x4*)lo = l;
+}
+
+template <class T, int R>
+__global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
+{
+    constexpr int V = DT - 2 * R;
+    constexpr int NK = T::NK;
+    // LDS: the transformed channels (fp32) + a scratch region shared by the
+    // forward stages (Xs, Yt) and the inverse stages (Zc)
+    constexpr int XH_FLOATS = T::C * DT * XH_P;
+    constexpr int SCRATCH_BF16 = 2 * DT * XS_P + 2 * DT * YT_P;
+    static_assert(2 * ZC_ROWS * ZC_P <= SCRATCH_BF16, "scratch too small");
+    __shared__ float xh[XH_FLOATS];
+    __shared__ __bf16 scr[SCRATCH_BF16];
+    __bf16* xs_hi = scr;
+    __bf16* xs_lo = scr + DT * XS_P;
+    __bf16* yt_hi = scr + 2 * DT * XS_P;
+    __bf16* yt_lo = yt_hi + DT * YT_P;
+    __bf16* zc_hi = scr;
+    __bf16* zc_lo = scr + ZC_ROWS * ZC_P;
+
+    const int H = g.H, W = g.W;
+    const size_t HW = (size_t)H * W;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tyi = tile / g.tiles_x, txi = tile - tyi * g.tiles_x;
+    const int y0 = tyi * V, x0 = txi * V;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = (lane >> 4) * 8, ld = (lane >> 4) * 4;
+    const bool single_wrap = (H >= DT) && (W >= DT);
+
+    // ---- forward transform of each source channel --------------------------
+    for (int s = 0; s < T::C; ++s) {
+        __syncthreads();
+        // stage the 64 x 64 window (wrapped) as bf16 hi / lo
+        for (int i = threadIdx.x; i < DT * DT / 4; i += 256) {
+            const int r = i / (DT / 4), c4 = (i % (DT / 4)) * 4;
+            f32x4 v;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int gy = y0 - R + r, gx = x0 - R + c4 + j;
+                wrap2(gy, gx, H, W, single_wrap);
+                v[j] = g.A[(size_t)s * HW + (size_t)gy * W + gx];
+            }
+            st4_split(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, v);
+        }
+        __syncthreads();
+        // GEMM1: wave w computes rows 16w..16w+15 of Y, all 8 column blocks
+        {
+            f32x4 acc[8];
+#pragma unroll
+            for (int n = 0; n < 8; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int k0 = 32 * ks + lk;
+                const bf16x8 ah = ld8(xs_hi + (16 * wave + lr) * XS_P + k0);
+                const bf16x8 al = ld8(xs_lo + (16 * wave + lr) * XS_P + k0);
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    const int row = 16 * n + lr;
+                    const bf16x8 bh = ld8(g.t.f1t + row * DT + k0);
+                    const bf16x8 bl = ld8(g.t.f1t + DT2 * DT + row * DT + k0);
+                    acc[n] = mma3(ah, al, bh, bl, acc[n]);
+                }
+            }
+            // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 64][64 (c / 64) + i]
+#pragma unroll
+            for (int n = 0; n < 8; ++n) {
+                const int c = 16 * n + lr;
+                const int off = (c % DT) * YT_P + DT * (c / DT) + 16 * wave + ld;
+                st4_split(yt_hi + off, yt_lo + off, acc[n]);
+            }
+        }
+        __syncthreads();
+        // GEMM2: wave w computes row blocks 2w, 2w+1 of Xh, all 4 column blocks
+        {
+            f32x4 acc[2][4];
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k0 = 32 * ks + lk;
+                bf16x8 ah[2], al[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int row = 16 * (2 * wave + m) + lr;
+                    ah[m] = ld8(g.t.f2 + row * DT2 + k0);
+                    al[m] = ld8(g.t.f2 + DT2 * DT2 + row * DT2 + k0);
+                }
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const bf16x8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
+                    const bf16x8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
+#pragma unroll
+                    for (int m = 0; m < 2; ++m) acc[m][n] = mma3(ah[m], al[m], bh, bl, acc[m][n]);
+                }
+            }
+            // Xh row r = 16 (2w + m) + ld + j, column f2 = 16n + lr  ->  xh[s][f2][r]
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const int f2 = 16 * n + lr, r = 16 * (2 * wave + m) + ld;
+                    *(f32x4*)(xh + (s * DT + f2) * XH_P + r) = acc[m][n];
+                }
+        }
+    }
+    __syncthreads();
+
+    // ---- per kernel: spectral product and inverse transform -----------------
+    // GEMM3 column blocks (of 2V rows of Z, padded to 80) handled by this wave:
+    // 0 and 4 for wave 0, wave w otherwise; their B fragments stay in registers.
+    constexpr int NB3 = (2 * V + 15) / 16;
+    static_assert(NB3 == 5, "GEMM3 is laid out for 5 column blocks");
+    const int nb3 = (wave == 0) ? 2 : 1;
+    bf16x8 b3h[2][4], b3l[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int nt = (q == 0) ? wave : 4;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int row = 16 * nt + lr, k0 = 32 * ks + lk;
+            b3h[q][ks] = ld8(g.t.f3 + row * DT2 + k0);
+            b3l[q][ks] = ld8(g.t.f3 + 80 * DT2 + row * DT2 + k0);
+        }
+    }
+    // GEMM4: wave w < 3 handles output column block w; B fragments in registers
+    bf16x8 b4h[4], b4l[4];
+    {
+        const int row = 16 * (wave < 3 ? wave : 0) + lr;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            b4h[ks] = ld8(g.t.f4t + row * DT2 + 32 * ks + lk);
+            b4l[ks] = ld8(g.t.f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
+        }
+    }
+
+#pragma unroll 1
+    for (int k = 0; k < NK; ++k) {
+        const int s = T::src[k];
+        const float* kh = g.t.khat + (size_t)k * DT * DT;
+        // GEMM3: Z^T (64 x 80) = Ust^T (64 x 128) F3^T; wave handles all 4 row blocks
+        f32x4 acc[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k0 = 32 * ks + lk;          // f1 + 64 (im)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int f2 = 16 * m + lr;
+                const f32x4 x0v = *(const f32x4*)(xh + (s * DT + f2) * XH_P + k0);
+                const f32x4 x1v = *(const f32x4*)(xh + (s * DT + f2) * XH_P + k0 + 4);
+                const f32x4 k0v = *(const f32x4*)(kh + f2 * DT + (k0 % DT));
+                const f32x4 k1v = *(const f32x4*)(kh + f2 * DT + (k0 % DT) + 4);
+                float u8[8];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    u8[j] = x0v[j] * k0v[j];
+                    u8[4 + j] = x1v[j] * k1v[j];
+                }
+                bf16x8 ah, al;
+                split8(u8, ah, al);
+                acc[0][m] = mma3(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
+                if (nb3 == 2) acc[1][m] = mma3(ah, al, b3h[1][ks], b3l[1][ks], acc[1][m]);
+            }
+        }
+        __syncthreads();    // previous kernel's GEMM4 finished reading Zc
+        // Z^T row f2 = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][64 (p' >= V) + f2]
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (q == 1 && nb3 != 2) break;
+            const int nt = (q == 0) ? wave : 4;
+            const int pp = 16 * nt + lr;
+            if (pp < 2 * V) {
+                const int p = (pp < V) ? pp : pp - V, col0 = (pp < V) ? 0 : DT;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int off = p * ZC_P + col0 + 16 * m + ld;
+                    st4_split(zc_hi + off, zc_lo + off, acc[q][m]);
+                }
+            }
+        }
+        __syncthreads();
+        // GEMM4: u (48 x 48) = Zc (48 x 128) F4; wave w < 3 computes column block w
+        if (wave < 3) {
+            f32x4 o[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int k0 = 32 * ks + lk;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const int row = 16 * m + lr;
+                    const bf16x8 ah = ld8(zc_hi + row * ZC_P + k0);
+                    const bf16x8 al = ld8(zc_lo + row * ZC_P + k0);
+                    o[m] = mma3(ah, al, b4h[ks], b4l[ks], o[m]);
+                }
+            }
+            // u row p = 16m + ld + j, column q = 16w + lr
+            const int qx = 16 * wave + lr;
+            const int gx = x0 + qx;
+            if (qx < V && gx < W) {
+                float* uk = g.U + (size_t)k * HW;
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int p = 16 * m + ld + j, gy = y0 + p;
+                        if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j];
+                    }
+            }
+        }
+    }
+}
+
+template <class T, int R>
+hipError_t launch_dft(const DftArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((dft_conv_kernel<T, R>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+typedef hipError_t (*dft_launch_fn)(const DftArgs&, hipStream_t);
+
+static dft_launch_fn find_dft(int table, int R)
+{
+    if (table == TABLE_3x15 && R == 12) return &launch_dft<Table3x15, 12>;
+    if (table == TABLE_3x15 && R == 13) return &launch_dft<Table3x15, 13>;
+    if (table == TABLE_1x1 && R == 12) return &launch_dft<Table1x1, 12>;
+    if (table == TABLE_1x1 && R == 13) return &launch_dft<Table1x1, 13>;
+    return nullptr;
+}
+
+bool conv_form_supported(int conv, int table, int R)
+{
+    return conv == LENIA_CONV_DFT_SPLIT_BF16 && find_dft(table, R) != nullptr;
+}
+
+int dft_valid_side(int R) { return DT - 2 * R; }
+
+// Round-to-nearest-even float -> bf16 bits, on the host.
+static uint16_t bf16_bits(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static float bf16_value(uint16_t b)
+{
+    const uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Host tables of the DFT form: the four transform matrices (FP64, split into
+// bf16 hi / lo) and the kernels' real spectra on the 64 x 64 torus.
+lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
+                              std::vector<void*>& keep)
+{
+    const int R = w.R, V = DT - 2 * R;
+    const double tw = 2.0 * M_PI / DT;
+    auto C = [&](int f, int i) { return std::cos(tw * (double)((f * i) % DT)); };
+    auto S = [&](int f, int i) { return std::sin(tw * (double)((f * i) % DT)); };
+    std::vector<double> f1t(DT2 * DT), f2(DT2 * DT2), f3(80 * DT2, 0.0), f4t(ZC_ROWS * DT2, 0.0);
+    for (int c = 0; c < DT2; ++c)          // [C | -S]^T : row c, column j
+        for (int j = 0; j < DT; ++j) f1t[c * DT + j] = (c < DT) ? C(c, j) : -S(c - DT, j);
+    for (int r = 0; r < DT2; ++r)
+        for (int k = 0; k < DT2; ++k) {
+            const int rr = r % DT, kk = k % DT;
+            double v;
+            if (r < DT) v = (k < DT) ? C(rr, kk) : S(rr, kk);
+            else v = (k < DT) ? -S(rr, kk) : C(rr, kk);
+            f2[r * DT2 + k] = v;
+        }
+    for (int pp = 0; pp < 2 * V; ++pp)     // rows of [Z_re; Z_im]
+        for (int k = 0; k < DT2; ++k) {
+            const int p = pp % V, f1 = k % DT;
+            const double c = C(f1, R + p), sn = S(f1, R + p);
+            double v;
+            if (pp < V) v = (k < DT) ? c : -sn;
+            else v = (k < DT) ? sn : c;
+            f3[pp * DT2 + k] = v;
+        }
+    for (int q = 0; q < V; ++q)            // [C'_V; -S'_V]^T : row q, column k
+        for (int k = 0; k < DT2; ++k) {
+            const int f2i = k % DT;
+            f4t[q * DT2 + k] = (k < DT) ? C(f2i, R + q) : -S(f2i, R + q);
+        }
+    auto split = [&](const std::vector<double>& m) {
+        uint16_t* out = new uint16_t[2 * m.size()];
+        for (size_t i = 0; i < m.size(); ++i) {
+            const uint16_t h = bf16_bits((float)m[i]);
+            out[i] = h;
+            out[m.size() + i] = bf16_bits((float)(m[i] - (double)bf16_value(h)));
+        }
+        keep.push_back(out);
+        return out;
+    };
+    // kernel spectra: Khat[k][f2][f1] = sum_d K~(d) cos(2 pi (f1 dy + f2 dx)/64) / 64^2
+    std::vector<double> kt((size_t)DT * DT);
+    float* kh = new float[(size_t)w.NK * DT * DT];
+    keep.push_back(kh);
+    for (int k = 0; k < w.NK; ++k) {
+        const int B = w.n_shells[k];
+        const double* beta = &w.beta[3 * k];
+        const double z = raw_kernel_sum(R, B, beta);
+        std::fill(kt.begin(), kt.end(), 0.0);
+        for (int dy = -R; dy <= R; ++dy)
+            for (int dx = -R; dx <= R; ++dx)
+                kt[((dy + DT) % DT) * DT + (dx + DT) % DT] += raw_kernel_tap(R, B, beta, dy, dx) / z;
+        // separable real DFT: first over dx (f2), then dy (f1); the kernel is even
+        std::vector<double> t1((size_t)DT * DT, 0.0);
+        for (int y = 0; y < DT; ++y)
+            for (int f = 0; f < DT; ++f) {
+                double acc = 0.0;
+                for (int x = 0; x < DT; ++x) acc += kt[y * DT + x] * C(f, x);
+                t1[y * DT + f] = acc;
+            }
+        for (int f2i = 0; f2i < DT; ++f2i)
+            for (int f1 = 0; f1 < DT; ++f1) {
+                double acc = 0.0;
+                for (int y = 0; y < DT; ++y) acc += t1[y * DT + f2i] * C(f1, y);
+                kh[((size_t)k * DT + f2i) * DT + f1] = (float)(acc / (DT * DT));
+            }
+    }
+    const struct {
+        const std::vector<double>* m;
+        __bf16** dst;
+    } mats[4] = {{&f1t, (__bf16**)&w.dft_f1t}, {&f2, (__bf16**)&w.dft_f2},
+                 {&f3, (__bf16**)&w.dft_f3}, {&f4t, (__bf16**)&w.dft_f4t}};
+    for (const auto& mm : mats) {
+        uint16_t* host = split(*mm.m);
+        const size_t bytes = 2 * mm.m->size() * sizeof(uint16_t);
+        void* d = nullptr;
+        if (hipMalloc(&d, bytes) != hipSuccess)
+            return set_error(LENIA_ERR_OUT_OF_MEMORY, "DFT tables");
+        p->allocations.push_back(d);
+        p->ws_bytes += bytes;
+        *mm.dst = (__bf16*)d;
+        hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "uploading DFT tables");
+    }
+    const size_t kbytes = (size_t)w.NK * DT * DT * sizeof(float);
+    void* d = nullptr;
+    if (hipMalloc(&d, kbytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "spectra");
+    p->allocations.push_back(d);
+    p->ws_bytes += kbytes;
+    w.dft_khat = (float*)d;
+    hipError_t e = hipMemcpyAsync(d, kh, kbytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "uploading spectra");
+    const size_t ubytes = (size_t)w.NK * w.cells() * sizeof(float);
+    if (hipMalloc(&d, ubytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "potentials");
+    p->allocations.push_back(d);
+    p->ws_bytes += ubytes;
+    w.dft_u = (float*)d;
+    return LENIA_OK;
+}
+
+hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const float* A,
+                                 float* U, hipStream_t s)
+{
+    DftArgs a{};
+    a.A = A;
+    a.U = U;
+    a.t.f1t = (const __bf16*)w.dft_f1t;
+    a.t.f2 = (const __bf16*)w.dft_f2;
+    a.t.f3 = (const __bf16*)w.dft_f3;
+    a.t.f4t = (const __bf16*)w.dft_f4t;
+    a.t.khat = w.dft_khat;
+    a.H = w.H;
+    a.W = w.W;
+    const int V = DT - 2 * w.R;
+    a.tiles_x = (w.W + V - 1) / V;
+    a.n_tiles = a.tiles_x * ((w.H + V - 1) / V);
+    dft_launch_fn fn = find_dft(p->table, p->R);
+    if (!fn) return hipErrorInvalidValue;
+    return fn(a, s);
+}
+
+}  // namespace lenia

@@ -81,7 +81,8 @@ struct Table3x15 {
 
 enum TableId { TABLE_1x1 = 0, TABLE_3x15 = 1 };
 
-enum Mode { MODE_GLOBAL = 0, MODE_LOCAL_READONLY = 1, MODE_LOCAL_UPDATE = 2 };
+enum Mode { MODE_GLOBAL = 0, MODE_LOCAL_READONLY = 1, MODE_LOCAL_UPDATE = 2,
+            MODE_POTENTIALS = 3 /* write u_k to U_save only */ };
 
 constexpr int kMaxK = 16;
 

@@ -22,13 +22,6 @@ using namespace lenia;
 
 namespace lenia {
 
-bool conv_form_supported(int conv, int table, int R)
-{
-    (void)conv;
-    (void)table;
-    (void)R;
-    return false;
-}
 
 WorldArgs WorldPlan::args_template() const
 {
@@ -461,6 +454,8 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     std::vector<void*> keep;
     lenia_status st = LENIA_OK;
     for (int i = 0; i < n && st == LENIA_OK; ++i) st = build_world(p, &ds[i], p->worlds[i], s, keep);
+    if (st == LENIA_OK && p->conv == LENIA_CONV_DFT_SPLIT_BF16)
+        st = build_dft_tables(p, p->worlds[0], s, keep);
     if (st == LENIA_OK && batched) {
         p->grid = 2 * device_cus(p->device);
         for (int ph = 0; ph < 2 && st == LENIA_OK; ++ph) {
@@ -502,7 +497,7 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
         hipError_t e = hipStreamSynchronize(s);   // host table copies must outlive the upload
         if (e != hipSuccess) st = hip_fail(e, "plan upload");
     }
-    for (void* q : keep) delete[] (float*)q;
+    for (void* q : keep) delete[] (char*)q;
     if (st != LENIA_OK) {
         free_all(p);
         delete p;
@@ -560,6 +555,8 @@ lenia_status lenia_plan_get_info(lenia_plan_t p, lenia_plan_info* info)
     info->conv = p->conv;
     info->tile_y = p->tile_y;
     info->tile_x = p->tile_x;
+    if (p->conv == LENIA_CONV_DFT_SPLIT_BF16)
+        info->tile_y = info->tile_x = dft_valid_side(p->R);
     info->n_worlds = (int32_t)p->worlds.size();
     int64_t cells = 0;
     for (const WorldPlan& w : p->worlds) cells += (int64_t)w.cells();
@@ -636,7 +633,20 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
             a.P = upd ? curP : P_in;
             a.A_out = nA;
             a.P_out = upd ? nP : nullptr;
-            hipError_t e = p->step_fn(a, w.mode, s);
+            hipError_t e;
+            if (p->conv == LENIA_CONV_DFT_SPLIT_BF16) {
+                // potentials on the MFMA units into the saved buffer (or the
+                // plan's workspace), then the per-cell epilogue reads them
+                float* U = saved ? (float*)saved : w.dft_u;
+                e = launch_dft_potentials(p, w, curA, U, s);
+                if (e == hipSuccess) {
+                    WorldArgs ea = a;
+                    ea.U_save = nullptr;
+                    e = find_epilogue_launcher(p->table)(ea, U, w.mode, s);
+                }
+            } else {
+                e = p->step_fn(a, w.mode, s);
+            }
             if (e != hipSuccess) return hip_fail(e, "step launch");
             curA = nA;
             curP = nP;
@@ -650,6 +660,35 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
         return LENIA_OK;
     } catch (...) {
         return set_error(LENIA_ERR_STATE, "exception in lenia_step");
+    }
+}
+
+lenia_status lenia_potentials(lenia_plan_t p, const float* A, float* U, void* stream)
+{
+    try {
+        if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
+        if (p->batched) return set_error(LENIA_ERR_STATE, "batched plan");
+        if (!A || !U) return set_error(LENIA_ERR_INVALID_ARG, "A / U is NULL");
+        if (((uintptr_t)A | (uintptr_t)U) & 3)
+            return set_error(LENIA_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+        if ((const void*)A == (const void*)U)
+            return set_error(LENIA_ERR_INVALID_ARG, "U must not alias A");
+        WorldPlan& w = p->worlds[0];
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e;
+        if (p->conv == LENIA_CONV_DFT_SPLIT_BF16) {
+            e = launch_dft_potentials(p, w, A, U, s);
+        } else {
+            WorldArgs a = w.args_template();
+            a.tiles_x = tiles_of(w.W, p->tile_x);
+            a.n_tiles = tiles_of(w.H, p->tile_y) * a.tiles_x;
+            a.A = A;
+            a.U_save = U;
+            e = p->step_fn(a, MODE_POTENTIALS, s);
+        }
+        return e == hipSuccess ? LENIA_OK : hip_fail(e, "potentials launch");
+    } catch (...) {
+        return set_error(LENIA_ERR_STATE, "exception in lenia_potentials");
     }
 }
 

@@ -22,6 +22,11 @@ double raw_kernel_sum(int R, int B, const double* beta);
 void orbit_list(int R, std::vector<int>& a, std::vector<int>& b);
 int orbit_size(int a, int b);
 bool conv_form_supported(int conv, int table, int R);
+int dft_valid_side(int R);
+struct WorldPlan;
+lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s, std::vector<void*>& keep);
+hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const float* A, float* U,
+                                 hipStream_t s);
 
 // One world of a plan, with its descriptor arrays copied.
 struct WorldPlan {
@@ -37,6 +42,12 @@ struct WorldPlan {
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
     float* d_bt = nullptr;         // the same in the step kernel's orbit order
     int* d_nshells = nullptr;      // [NK]
+    void* dft_f1t = nullptr;       // DFT form: transform matrices (bf16 hi / lo),
+    void* dft_f2 = nullptr;        //   kernel spectra and the potentials workspace
+    void* dft_f3 = nullptr;
+    void* dft_f4t = nullptr;
+    float* dft_khat = nullptr;
+    float* dft_u = nullptr;        // [NK][H][W]
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
     float* ws_P = nullptr;         // [3][NK][H][W] (gene update only)
     size_t cells() const { return (size_t)H * W; }
@@ -51,6 +62,10 @@ struct BackwardWs {
     float* part = nullptr;         // [n_tiles][NK][3] beta-gradient partials
     int n_part = 0;
 };
+
+typedef hipError_t (*epilogue_launch_fn)(const WorldArgs& w, const float* U, int mode,
+                                         hipStream_t s);
+epilogue_launch_fn find_epilogue_launcher(int table);
 
 }  // namespace lenia
 

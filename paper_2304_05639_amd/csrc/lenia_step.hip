@@ -16,6 +16,7 @@
 
 #include "lenia_device.h"
 #include "lenia_internal.h"
+#include "lenia_plan.h"
 
 namespace lenia {
 
@@ -281,6 +282,16 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const float* c = sA + (ly + R) * PITCH + (lx + R);
     float u[2][NK];
     conv_pair<T, R, PITCH, CHS>(c, (cfloat*)wd.wt, u);
+    if (mode == MODE_POTENTIALS) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (gy + q < H) {
+                const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
+#pragma unroll
+                for (int k = 0; k < NK; ++k) (wd.U_save + (size_t)k * HW)[o] = u[q][k];
+            }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (gy + q < H) {
@@ -299,12 +310,51 @@ __global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_kernel(Wo
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA);
 }
 
+// Epilogue of a step whose potentials were computed elsewhere (the MFMA DFT
+// form): one thread per cell reads u_k from U.
+template <class T>
+__global__ __launch_bounds__(256) void epilogue_kernel(WorldArgs wd, const float* __restrict__ U,
+                                                       int mode)
+{
+    const uint32_t HW = (uint32_t)wd.H * (uint32_t)wd.W;
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= HW) return;
+    const int gy = (int)(idx / (uint32_t)wd.W), gx = (int)(idx - (uint32_t)gy * wd.W);
+    float u[T::NK], a[T::C];
+#pragma unroll
+    for (int k = 0; k < T::NK; ++k) u[k] = (U + (size_t)k * HW)[idx];
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) a[c] = (wd.A + (size_t)c * HW)[idx];
+    epilogue_cell<T>(wd, mode, u, a, gy, gx);
+}
+
+template <class T>
+hipError_t launch_epilogue(const WorldArgs& w, const float* U, int mode, hipStream_t s)
+{
+    const unsigned cells = (unsigned)w.H * (unsigned)w.W;
+    hipLaunchKernelGGL((epilogue_kernel<T>), dim3((cells + 255) / 256), dim3(256), 0, s, w, U, mode);
+    return hipGetLastError();
+}
+
+epilogue_launch_fn find_epilogue_launcher(int table)
+{
+    return (table == TABLE_3x15) ? &launch_epilogue<Table3x15> : &launch_epilogue<Table1x1>;
+}
+
 // Persistent form: a fixed grid walks the (world, tile) work list.
 template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
-    for (int i = blockIdx.x; i < bl.n_items; i += gridDim.x) {
+    // XCD-aware walk: the work list (tiles of a world in row order) is cut into
+    // 8 contiguous chunks, one per XCD, so that neighbouring tiles, whose halos
+    // overlap, are processed by workgroups sharing an L2
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int per_xcd = (gridDim.x + 7 - xcd) >> 3;        // workgroups on this XCD
+    const int chunk = (bl.n_items + 7) >> 3;
+    const int begin = xcd * chunk;
+    const int end = min(bl.n_items, begin + chunk);
+    for (int i = begin + slot; i < end; i += per_xcd) {
         const int2 it = bl.items[i];
         process_tile<T, R, TY, TX>(bl.worlds[it.x], it.y, mode, sA);
         __syncthreads();   // LDS reuse by the next item

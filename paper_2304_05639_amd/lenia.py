@@ -21,7 +21,7 @@ CONV_AUTO, CONV_DIRECT_F32, CONV_DFT_SPLIT_BF16, CONV_DFT_SPLIT_F16 = range(4)
 FLAG_AUTOTUNE = 1
 
 API = ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan", "lenia_plan_batched",
-       "lenia_step", "lenia_step_batched", "lenia_saved_bytes", "lenia_backward",
+       "lenia_step", "lenia_step_batched", "lenia_potentials", "lenia_saved_bytes", "lenia_backward",
        "lenia_plan_get_info", "lenia_plan_destroy", "lenia_status_str", "lenia_last_error")
 
 
@@ -71,6 +71,7 @@ def lib():
         L.lenia_plan_batched.argtypes = [C.POINTER(Desc), C.c_int32, vp, C.POINTER(vp)]
         L.lenia_step.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp, vp]
         L.lenia_step_batched.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_int32, vp]
+        L.lenia_potentials.argtypes = [vp, vp, vp, vp]
         L.lenia_saved_bytes.argtypes = [vp]
         L.lenia_saved_bytes.restype = C.c_size_t
         L.lenia_backward.argtypes = [vp] + [vp] * 8 + [vp]
@@ -81,7 +82,8 @@ def lib():
         L.lenia_last_error.restype = C.c_char_p
         for name in ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan",
                      "lenia_plan_batched", "lenia_step", "lenia_step_batched",
-                     "lenia_backward", "lenia_plan_get_info", "lenia_plan_destroy"):
+                     "lenia_potentials", "lenia_backward", "lenia_plan_get_info",
+                     "lenia_plan_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -225,6 +227,17 @@ class Plan:
                                 _ptr(P_out) if self.update else None, int(n_steps),
                                 _ptr(saved), C.c_void_p(_stream(stream))), "lenia_step")
         return A_out, (P_out if self.update else P)
+
+    def potentials(self, A, U=None, stream=None):
+        """u_k = K~_k * A_src(k) for every kernel: tensor [NK, H, W]."""
+        import torch
+        _check_tensor(A, (self.C, self.H, self.W), "A")
+        if U is None:
+            U = torch.empty(self.NK, self.H, self.W, dtype=torch.float32, device=A.device)
+        _check_tensor(U, (self.NK, self.H, self.W), "U")
+        _check(lib().lenia_potentials(self._h, _ptr(A), _ptr(U), C.c_void_p(_stream(stream))),
+               "lenia_potentials")
+        return U
 
     def backward(self, A_t, P_t, saved, gA_next, gP_next, gA_t=None, gP_t=None, gbeta=None,
                  stream=None):

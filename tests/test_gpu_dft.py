@@ -1,0 +1,109 @@
+"""GPU parity of the MFMA DFT-as-GEMM form (split-bf16 operands, FP32
+accumulation) against the FP64 oracle.  The potentials carry the form's
+rounding (about 16 significant bits per product, four transform stages), so
+they are compared with TOL_U; the state after the growth mapping, which can
+amplify a potential error by up to dt * max|G'| (24 at s = 0.01, dt = 0.2), is
+compared with TOL_STATE_DFT over cells whose alpha decision is not within
+the alpha-ambiguity band of the cutoff."""
+import numpy as np
+import pytest
+
+from paper_2304_05639_amd import inputs
+
+from gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = 2e-5
+TOL_STATE_DFT = 5e-4
+AMB_TAU = 2e-5        # alpha-ambiguity band for this form (above its potential error)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_05639_amd import lenia
+    lenia.lib()
+    return lenia
+
+
+def _run(L, w, n_steps=1):
+    import torch
+    plan = L.Plan(w, conv=L.CONV_DFT_SPLIT_BF16)
+    assert plan.info().conv == L.CONV_DFT_SPLIT_BF16
+    saved = plan.new_saved() if n_steps == 1 else None
+    A1, P1 = plan.step(dev(w.A), dev(w.P) if w.P is not None else None, n_steps=n_steps,
+                       saved=saved)
+    torch.cuda.synchronize()
+    u = host(plan.saved_views(saved)[0]) if saved is not None else None
+    return host(A1), (host(P1) if P1 is not None else None), u
+
+
+@pytest.mark.parametrize("H,W,seed,R", [(64, 64, 401, 12), (100, 150, 402, 12), (16, 16, 403, 12),
+                                        (81, 120, 404, 13), (512, 512, 405, 12)])
+def test_dft_potentials_and_state(L, oracle, H, W, seed, R):
+    w = inputs.test_world(H, W, seed=seed, n_blobs=max(1, H * W // 600), R=R)
+    d = oracle.Desc(w.H, w.W, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta, w.dt, 1, 1,
+                    tau=AMB_TAU)
+    A1, P1, u = _run(L, w)
+    r = oracle.step(d, w.A, w.P)
+    eu = float(np.abs(u - r["U"]).max())
+    ok = (r["amb"] & 1) == 0
+    eA = float(np.abs(A1 - r["A"])[:, ok].max())
+    eP = float(np.abs(P1 - r["P"])[:, :, ok].max())
+    print(f"DFT {H}x{W} R={R}: u err {eu:.2e}  A' err {eA:.2e}  P' err {eP:.2e}  "
+          f"ambiguous {int((~ok).sum())}")
+    assert eu <= TOL_U
+    assert eA <= TOL_STATE_DFT and eP <= TOL_STATE_DFT
+
+
+def test_dft_global_single_channel(L, oracle):
+    w = inputs.config1()
+    d = oracle.Desc.from_world(w)
+    A1, _, u = _run(L, w)
+    r = oracle.step(d, w.A)
+    eu = float(np.abs(u - r["U"]).max())
+    eA = float(np.abs(A1 - r["A"]).max())
+    print(f"DFT global 64x64 R=13: u err {eu:.2e}  A' err {eA:.2e}")
+    assert eu <= TOL_U and eA <= TOL_STATE_DFT
+
+
+def test_dft_deterministic_and_multistep(L):
+    w = inputs.test_world(128, 96, seed=406, n_blobs=6)
+    a = _run(L, w, n_steps=3)
+    b = _run(L, w, n_steps=3)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_dft_close_to_direct_form(L):
+    """The two forms compute the same convolution: their states after one step
+    differ by the DFT form's rounding only."""
+    import torch
+    w = inputs.test_world(200, 256, seed=407, n_blobs=20)
+    pd = L.Plan(w)
+    pf = L.Plan(w, conv=L.CONV_DFT_SPLIT_BF16)
+    sd, sf = pd.new_saved(), pf.new_saved()
+    pd.step(dev(w.A), dev(w.P), saved=sd)
+    pf.step(dev(w.A), dev(w.P), saved=sf)
+    torch.cuda.synchronize()
+    ud, uf = host(pd.saved_views(sd)[0]), host(pf.saved_views(sf)[0])
+    assert np.abs(ud - uf).max() <= TOL_U
+
+
+def test_potentials_entry_point(L, oracle):
+    """lenia_potentials: u_k for every kernel, both forms, against the oracle."""
+    import torch
+    w = inputs.test_world(96, 160, seed=408, n_blobs=10)
+    r = oracle.step(oracle.Desc.from_world(w), w.A, w.P)
+    for conv, tol in ((L.CONV_DIRECT_F32, 2e-6), (L.CONV_DFT_SPLIT_BF16, TOL_U)):
+        plan = L.Plan(w, conv=conv)
+        U = plan.potentials(dev(w.A))
+        torch.cuda.synchronize()
+        err = float(np.abs(host(U) - r["U"]).max())
+        print(f"potentials conv={conv}: max err {err:.2e}")
+        assert err <= tol
+    A = dev(w.A)
+    assert L.lib().lenia_potentials(plan.handle, A.data_ptr(), A.data_ptr(), None) == \
+        L.ERR_INVALID_ARG                      # U must not alias A
