@@ -189,6 +189,8 @@ def main():
                          "split-bf16 DFT-as-GEMM form on MFMA")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-dft", action="store_true", help="skip the MFMA DFT-form leg")
+    ap.add_argument("--only", choices=["ratio", "batched", "dft"], default=None,
+                    help="run a single secondary leg (for profiling) and print its JSON")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB fill, copy and sum (reference kernels for the "
                          "HBM byte counters)")
@@ -204,7 +206,16 @@ def main():
     import torch
     from paper_2304_05639_amd import inputs, lenia
 
+    if args.only == "ratio":
+        print(json.dumps({"bwd_fwd_ratio": backward_forward_ratio()}), flush=True)
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": batched_throughput()}), flush=True)
+        return
     world = inputs.config3()
+    if args.only == "dft":
+        print(json.dumps({"dft_split_bf16": dft_form(world)}), flush=True)
+        return
     cells = world.H * world.W
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
     conv = lenia.CONV_DFT_SPLIT_BF16 if args.conv == "dft" else lenia.CONV_AUTO

@@ -67,16 +67,13 @@ __global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
     for (int c = 0; c < T::C; ++c) a[c] = (b.A + (size_t)c * HW)[idx];
 
     if (!alpha) {
-        // no growth: z = A, P' = 0
+        // no growth: z = A, P' = 0.  ubar and numbar vanish here; the gather
+        // pass masks them by alpha instead of reading stored zeros.
 #pragma unroll
         for (int c = 0; c < T::C; ++c) {
             const float g1 = (b.gA1 + (size_t)c * HW)[idx];
             (b.gA + (size_t)c * HW)[idx] = (a[c] >= 0.f && a[c] <= 1.f) ? g1 : 0.f;
         }
-#pragma unroll
-        for (int k = 0; k < NK; ++k) (b.ubar + (size_t)k * HW)[idx] = 0.f;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) (b.numbar + (size_t)q * HW)[idx] = 0.f;
         return;
     }
 
@@ -157,58 +154,68 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// Sum of one tap over both cells of the pair for NPL planes: v[p][q].
-template <int NPL, int PITCH, int CHS>
-__device__ __forceinline__ void tap_load_planes(float (&v)[NPL][2], const float* p)
+// Values of one tap for NPL planes and the thread's Q cells: v[plane][cell].
+template <int NPL, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void tap_load_planes(float (&v)[NPL][Q], const float* p)
 {
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) v[pl][q] = p[pl * CHS + q * PITCH];
+        for (int q = 0; q < Q; ++q) v[pl][q] = p[pl * CHS + q * PITCH];
 }
 
-template <int NPL, int PITCH, int CHS>
-__device__ __forceinline__ void quad_planes(float (&sum)[NPL][2], const float* p0, const float* p1,
+template <int NPL, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void quad_planes(float (&sum)[NPL][Q], const float* p0, const float* p1,
                                             const float* p2, const float* p3)
 {
-    float v0[NPL][2], v1[NPL][2], v2[NPL][2], v3[NPL][2];
-    tap_load_planes<NPL, PITCH, CHS>(v0, p0);
-    tap_load_planes<NPL, PITCH, CHS>(v1, p1);
-    tap_load_planes<NPL, PITCH, CHS>(v2, p2);
-    tap_load_planes<NPL, PITCH, CHS>(v3, p3);
+    float v0[NPL][Q], v1[NPL][Q], v2[NPL][Q], v3[NPL][Q];
+    tap_load_planes<NPL, Q, PITCH, CHS>(v0, p0);
+    tap_load_planes<NPL, Q, PITCH, CHS>(v1, p1);
+    tap_load_planes<NPL, Q, PITCH, CHS>(v2, p2);
+    tap_load_planes<NPL, Q, PITCH, CHS>(v3, p3);
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) sum[pl][q] = (v0[pl][q] + v1[pl][q]) + (v2[pl][q] + v3[pl][q]);
+        for (int q = 0; q < Q; ++q) sum[pl][q] = (v0[pl][q] + v1[pl][q]) + (v2[pl][q] + v3[pl][q]);
 }
 
 // One orbit: transpose-convolution FMAs for the KPS ubar planes (weights w),
 // and the shell-height coefficient FMAs on the A plane (index KPS):
 // v[q][j][i] += bcoef_{k_j, i}(t) * (orbit sum of A at cell q).
-template <class T, int NPL>
-__device__ __forceinline__ void orbit_bwd(float (&g)[2], float (&v)[2][T::KPS][3],
-                                          const float (&sum)[NPL][2], cfloat* w, cfloat* bc)
+template <class T, int NPL, int Q>
+__device__ __forceinline__ void orbit_bwd(float (&g)[Q], float (&v)[Q][T::KPS][3],
+                                          const float (&sum)[NPL][Q], cfloat* w, cfloat* bc)
 {
 #pragma unroll
     for (int j = 0; j < T::KPS; ++j) {
         const float wj = w[j];
-        g[0] = fmaf(wj, sum[j][0], g[0]);
-        g[1] = fmaf(wj, sum[j][1], g[1]);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g[q] = fmaf(wj, sum[j][q], g[q]);
     }
 #pragma unroll
     for (int j = 0; j < T::KPS; ++j)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float c = bc[j * 3 + i];
-            v[0][j][i] = fmaf(c, sum[NPL - 1][0], v[0][j][i]);
-            v[1][j][i] = fmaf(c, sum[NPL - 1][1], v[1][j][i]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) v[q][j][i] = fmaf(c, sum[NPL - 1][q], v[q][j][i]);
         }
 }
 
+template <int TY, int TX>
+constexpr int bwd_cells_per_thread() { return (TY * TX <= 256) ? 1 : 2; }
+
+template <int TY, int TX>
+constexpr int bwd_threads() { return TY * TX / bwd_cells_per_thread<TY, TX>(); }
+
+// One workgroup per (tile, source channel s): the transposed convolution into
+// gA_s, the shell-height partials of the kernels reading s, and the diffusion
+// transpose of the gene planes q with q % C == s.
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
+__global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(BwdArgs b)
 {
-    constexpr int NT = TY * TX / 2;
+    constexpr int Q = bwd_cells_per_thread<TY, TX>();
+    constexpr int NT = bwd_threads<TY, TX>();
     constexpr int NWV = NT / 64;
     constexpr int KPS = T::KPS;
     constexpr int NPL = KPS + 1;
@@ -222,120 +229,125 @@ __global__ __launch_bounds__(TY * TX / 2) void bwd_gather_kernel(BwdArgs b)
 
     const int H = b.H, W = b.W;
     const size_t HW = (size_t)H * W;
+    const int s = blockIdx.y;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tyi = tile / b.tiles_x, txi = tile - tyi * b.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
-    const int ly = 2 * (threadIdx.x / TX), lx = threadIdx.x % TX;
+    const int ly = Q * (threadIdx.x / TX), lx = threadIdx.x % TX;
     const int gy = y0 + ly, gx = x0 + lx;
-    const bool valid0 = (gy < H) && (gx < W);
-    const bool valid1 = (gy + 1 < H) && (gx < W);
+    bool valid[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) valid[q] = (gy + q < H) && (gx < W);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    (void)lane;
     const float* c = sm + (ly + R) * PITCH + (lx + R);
 
-    float gsum[2][T::C];
-#pragma unroll 1
-    for (int s = 0; s < T::C; ++s) {
-        const float* src[NPL];
+    const float* src[NPL];
 #pragma unroll
-        for (int j = 0; j < KPS; ++j) src[j] = b.ubar + (size_t)T::kidx[s][j] * HW;
-        src[KPS] = b.A + (size_t)s * HW;
-        __syncthreads();
+    for (int j = 0; j < KPS; ++j) src[j] = b.ubar + (size_t)T::kidx[s][j] * HW;
+    src[KPS] = b.A + (size_t)s * HW;
+    // ubar is staged masked by alpha (only alpha cells hold it); A unmasked
+    if (b.mode == MODE_LOCAL_UPDATE)
+        stage_planes<NPL, R, TY, TX, NT, PITCH, CHS, KPS>(sm, src, H, W, y0, x0, b.alpha);
+    else
         stage_planes<NPL, R, TY, TX, NT, PITCH, CHS>(sm, src, H, W, y0, x0);
-        __syncthreads();
-        float uc[KPS][2];
+    __syncthreads();
+    float uc[KPS][Q];
 #pragma unroll
-        for (int j = 0; j < KPS; ++j) {
-            uc[j][0] = valid0 ? c[j * CHS] : 0.f;
-            uc[j][1] = valid1 ? c[j * CHS + PITCH] : 0.f;
-        }
-        float g[2] = {0.f, 0.f};
-        float v[2][KPS][3];
+    for (int j = 0; j < KPS; ++j)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < Q; ++q) uc[j][q] = valid[q] ? c[j * CHS + q * PITCH] : 0.f;
+    float g[Q];
+    float v[Q][KPS][3];
 #pragma unroll
-            for (int j = 0; j < KPS; ++j)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) v[q][j][i] = 0.f;
-        cfloat* w = (cfloat*)b.wt + s * 8;
-        cfloat* bc = (cfloat*)b.bt + s * 16;
-#pragma unroll 1
-        for (int a = 1; a < R; ++a, w += WS, bc += BS) {
-            float sum[NPL][2];
-            quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-            orbit_bwd<T, NPL>(g, v, sum, w, bc);
-        }
-#pragma unroll 1
-        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
-            float sum[NPL][2];
-            quad_planes<NPL, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
-                                         c - a * PITCH + a, c - a * PITCH - a);
-            orbit_bwd<T, NPL>(g, v, sum, w, bc);
-        }
-#pragma unroll 1
-        for (int a = 2; a < R; ++a) {
-#pragma unroll 1
-            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
-                float s0[NPL][2], s1[NPL][2], sum[NPL][2];
-                quad_planes<NPL, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
-                                             c - a * PITCH + bb, c - a * PITCH - bb);
-                quad_planes<NPL, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
-                                             c - bb * PITCH + a, c - bb * PITCH - a);
-#pragma unroll
-                for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
-                orbit_bwd<T, NPL>(g, v, sum, w, bc);
-            }
-        }
-        gsum[0][s] = g[0];
-        gsum[1][s] = g[1];
-        // shell-height partials of this tile: ubar at the cell times its
-        // coefficient-weighted orbit sums, reduced over the block in a fixed order
+    for (int q = 0; q < Q; ++q) {
+        g[q] = 0.f;
 #pragma unroll
         for (int j = 0; j < KPS; ++j)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const float pr = wave_sum(fmaf(uc[j][1], v[1][j][i], uc[j][0] * v[0][j][i]));
-                if (lane == 0) red[wave][j * 3 + i] = pr;
-            }
-        __syncthreads();
-        for (int e = threadIdx.x; e < KPS * 3; e += NT) {
-            float acc = 0.f;
+            for (int i = 0; i < 3; ++i) v[q][j][i] = 0.f;
+    }
+    cfloat* w = (cfloat*)b.wt + s * 8;
+    cfloat* bc = (cfloat*)b.bt + s * 16;
+#pragma unroll 1
+    for (int a = 1; a < R; ++a, w += WS, bc += BS) {
+        float sum[NPL][Q];
+        quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
+        orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+    }
+#pragma unroll 1
+    for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
+        float sum[NPL][Q];
+        quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
+                                        c - a * PITCH + a, c - a * PITCH - a);
+        orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+    }
+#pragma unroll 1
+    for (int a = 2; a < R; ++a) {
+#pragma unroll 1
+        for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
+            float s0[NPL][Q], s1[NPL][Q], sum[NPL][Q];
+            quad_planes<NPL, Q, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
+                                            c - a * PITCH + bb, c - a * PITCH - bb);
+            quad_planes<NPL, Q, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
+                                            c - bb * PITCH + a, c - bb * PITCH - a);
 #pragma unroll
-            for (int wv = 0; wv < NWV; ++wv) acc += red[wv][e];
-            const int k = T::kidx[s][e / 3];
-            b.part[((size_t)tile * T::NK + k) * 3 + (e % 3)] = acc;
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+            orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
         }
     }
-
-    // direct term from the cell pass + convolution transpose
+    // shell-height partials of this tile: ubar at the cell times its
+    // coefficient-weighted orbit sums, reduced over the block in a fixed order
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (q == 0 ? !valid0 : !valid1) continue;
-        const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
+    for (int j = 0; j < KPS; ++j)
 #pragma unroll
-        for (int s = 0; s < T::C; ++s) {
-            float* ga = b.gA + (size_t)s * HW;
-            ga[o] = ga[o] + gsum[q][s];
+        for (int i = 0; i < 3; ++i) {
+            float pr = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) pr = fmaf(uc[j][q], v[q][j][i], pr);
+            pr = wave_sum(pr);
+            if (lane == 0) red[wave][j * 3 + i] = pr;
         }
+    __syncthreads();
+    for (int e = threadIdx.x; e < KPS * 3; e += NT) {
+        float acc = 0.f;
+#pragma unroll
+        for (int wv = 0; wv < NWV; ++wv) acc += red[wv][e];
+        const int k = T::kidx[s][e / 3];
+        b.part[((size_t)tile * T::NK + k) * 3 + (e % 3)] = acc;
+    }
+
+    // direct term from the cell pass + convolution transpose into channel s
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (!valid[q]) continue;
+        const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
+        float* ga = b.gA + (size_t)s * HW;
+        ga[o] = ga[o] + g[q];
     }
     // transpose of the gene diffusion: gP(y) = sum over the disk of numbar(y + d);
     // numbar vanishes wherever alpha does, so cells whose 5-neighbourhood has
     // no alpha skip the reads
     if (b.mode == MODE_LOCAL_UPDATE) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q == 0 ? !valid0 : !valid1) continue;
+        for (int q = 0; q < Q; ++q) {
+            if (!valid[q]) continue;
             const Nbr nb = neighbours(gy + q, gx, H, W);
-            const bool any = b.alpha[nb.oc] | b.alpha[nb.ou] | b.alpha[nb.od] | b.alpha[nb.ol] |
-                             b.alpha[nb.orr];
-#pragma unroll
-            for (int pq = 0; pq < 3 * T::NK; ++pq) {
+            const bool au = b.alpha[nb.ou], al = b.alpha[nb.ol], ac = b.alpha[nb.oc],
+                       ar = b.alpha[nb.orr], ad = b.alpha[nb.od];
+            const bool any = au | al | ac | ar | ad;
+            for (int pq = s; pq < 3 * T::NK; pq += T::C) {
                 const float* nbp = b.numbar + (size_t)pq * HW;
-                float v = 0.f;
-                if (any) v = (((nbp[nb.ou] + nbp[nb.ol]) + nbp[nb.oc]) + nbp[nb.orr]) + nbp[nb.od];
-                (b.gP + (size_t)pq * HW)[nb.oc] = v;
+                float val = 0.f;
+                if (any) {
+                    // numbar holds values only where alpha does
+                    const float vu = au ? nbp[nb.ou] : 0.f, vl = al ? nbp[nb.ol] : 0.f;
+                    const float vc = ac ? nbp[nb.oc] : 0.f, vr = ar ? nbp[nb.orr] : 0.f;
+                    const float vd = ad ? nbp[nb.od] : 0.f;
+                    val = (((vu + vl) + vc) + vr) + vd;
+                }
+                (b.gP + (size_t)pq * HW)[nb.oc] = val;
             }
         }
     }
@@ -368,7 +380,8 @@ hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipS
     hipLaunchKernelGGL((bwd_cell_kernel<T>), dim3((cells + 255) / 256), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX>), dim3(a.n_tiles), dim3(TY * TX / 2), 0, s, a);
+    hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX>), dim3(a.n_tiles, T::C),
+                       dim3(bwd_threads<TY, TX>()), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bwd_beta_reduce_kernel, dim3(T::NK * 3), dim3(256), 0, s, a.part, a.n_tiles,

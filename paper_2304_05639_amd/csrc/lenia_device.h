@@ -62,9 +62,11 @@ __device__ __forceinline__ void wrap2(int& gy, int& gx, int H, int W, bool singl
 // top-left output cell is (y0, x0), plus an R-cell halo wrapped on the torus,
 // into dst[p * CHS + yy * PITCH + xx], using NT threads with all of a thread's
 // loads in flight before the LDS writes.
-template <int NPL, int R, int TY, int TX, int NT, int PITCH, int CHS>
+// The first NM planes are masked: a position whose mask byte is 0 stages 0.
+template <int NPL, int R, int TY, int TX, int NT, int PITCH, int CHS, int NM = 0>
 __device__ __forceinline__ void stage_planes(float* dst, const float* const (&src)[NPL], int H,
-                                             int W, int y0, int x0)
+                                             int W, int y0, int x0,
+                                             const uint8_t* mask = nullptr)
 {
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
     constexpr int NG = PY * PX;
@@ -80,8 +82,9 @@ __device__ __forceinline__ void stage_planes(float* dst, const float* const (&sr
             int gy = y0 + yy - R, gx = x0 + xx - R;
             wrap2(gy, gx, H, W, single_wrap);
             const uint32_t o = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+            const bool keep = (NM == 0) || (mask[o] != 0);
 #pragma unroll
-            for (int p = 0; p < NPL; ++p) v[it][p] = src[p][o];
+            for (int p = 0; p < NPL; ++p) v[it][p] = (p < NM && !keep) ? 0.f : src[p][o];
         }
     }
 #pragma unroll

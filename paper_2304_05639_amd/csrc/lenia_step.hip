@@ -37,8 +37,8 @@ namespace lenia {
 // cells are summed once per source channel and multiplied once per kernel.
 // `c` points at the upper cell in the LDS tile of channel 0; channel s is CHS
 // floats further.
-template <class T, int PITCH, int CHS>
-__device__ __forceinline__ void orbit_fma(float (&acc)[2][T::C][T::KPS], const float (&sum)[2][T::C],
+template <class T, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void orbit_fma(float (&acc)[Q][T::C][T::KPS], const float (&sum)[Q][T::C],
                                           cfloat* w)
 {
 #pragma unroll
@@ -46,57 +46,54 @@ __device__ __forceinline__ void orbit_fma(float (&acc)[2][T::C][T::KPS], const f
 #pragma unroll
         for (int j = 0; j < T::KPS; ++j) {
             const float wj = w[s * 8 + j];
-            acc[0][s][j] = fmaf(wj, sum[0][s], acc[0][s][j]);
-            acc[1][s][j] = fmaf(wj, sum[1][s], acc[1][s][j]);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) acc[q][s][j] = fmaf(wj, sum[q][s], acc[q][s][j]);
         }
 }
 
-// Sum over one tap of both cells and every channel: p points at the tap of
-// the upper cell in channel 0; channel s is CHS floats further, the lower cell
-// PITCH floats further.  With CHS and PITCH multiples of 64 floats all six
-// values come from one address register (ds_read2st64 pairs).
-template <class T, int PITCH, int CHS>
-__device__ __forceinline__ void tap_add(float (&sum)[2][T::C], const float* p)
+// Values of one tap for the thread's Q cells (c, c + PITCH, ...) and every
+// channel: p points at the tap of the first cell in channel 0; channel s is
+// CHS floats further.  With CHS and PITCH multiples of 64 floats all values
+// come from one address register (ds_read2st64 pairs).
+template <class T, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void tap_load(float (&v)[Q][T::C], const float* p)
 {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int s = 0; s < T::C; ++s) sum[q][s] += p[s * CHS + q * PITCH];
-}
-
-template <class T, int PITCH, int CHS>
-__device__ __forceinline__ void tap_load(float (&v)[2][T::C], const float* p)
-{
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int s = 0; s < T::C; ++s) v[q][s] = p[s * CHS + q * PITCH];
 }
 
 // sum = (t0 + t1) + (t2 + t3) for each (cell, channel)
-template <class T, int PITCH, int CHS>
-__device__ __forceinline__ void quad_sum(float (&sum)[2][T::C], const float* p0, const float* p1,
+template <class T, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void quad_sum(float (&sum)[Q][T::C], const float* p0, const float* p1,
                                          const float* p2, const float* p3)
 {
-    float v0[2][T::C], v1[2][T::C], v2[2][T::C], v3[2][T::C];
-    tap_load<T, PITCH, CHS>(v0, p0);
-    tap_load<T, PITCH, CHS>(v1, p1);
-    tap_load<T, PITCH, CHS>(v2, p2);
-    tap_load<T, PITCH, CHS>(v3, p3);
+    float v0[Q][T::C], v1[Q][T::C], v2[Q][T::C], v3[Q][T::C];
+    tap_load<T, Q, PITCH, CHS>(v0, p0);
+    tap_load<T, Q, PITCH, CHS>(v1, p1);
+    tap_load<T, Q, PITCH, CHS>(v2, p2);
+    tap_load<T, Q, PITCH, CHS>(v3, p3);
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int s = 0; s < T::C; ++s) sum[q][s] = (v0[q][s] + v1[q][s]) + (v2[q][s] + v3[q][s]);
 }
 
-template <class T, int R, int PITCH, int CHS>
-__device__ __forceinline__ void conv_pair(const float* c, cfloat* __restrict__ wt,
-                                          float (&u)[2][T::NK])
+// Potentials of Q vertically adjacent cells (c, c + PITCH, ...):
+//   u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
+// The offsets are walked orbit by orbit in three branch-free loops, in the
+// order of the weight table: axis orbits (a, 0), diagonal orbits (a, a), then
+// general orbits (a, b), 0 < b < a (all with a^2 + b^2 < R^2).  Each orbit's
+// cells are summed once per source channel and multiplied once per kernel.
+template <class T, int Q, int R, int PITCH, int CHS>
+__device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ wt,
+                                           float (&u)[Q][T::NK])
 {
     constexpr int WS = T::C * 8;   // weights per orbit
-    float acc[2][T::C][T::KPS];
+    float acc[Q][T::C][T::KPS];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int s = 0; s < T::C; ++s)
 #pragma unroll
@@ -105,45 +102,43 @@ __device__ __forceinline__ void conv_pair(const float* c, cfloat* __restrict__ w
     // axis orbits: (+-a, 0), (0, +-a)
 #pragma unroll 1
     for (int a = 1; a < R; ++a, w += WS) {
-        float sum[2][T::C];
-        quad_sum<T, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-        orbit_fma<T, PITCH, CHS>(acc, sum, w);
+        float sum[Q][T::C];
+        quad_sum<T, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
+        orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
     }
     // diagonal orbits: (+-a, +-a)
 #pragma unroll 1
     for (int a = 1; 2 * a * a < R * R; ++a, w += WS) {
-        float sum[2][T::C];
-        quad_sum<T, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a, c - a * PITCH + a,
-                                c - a * PITCH - a);
-        orbit_fma<T, PITCH, CHS>(acc, sum, w);
+        float sum[Q][T::C];
+        quad_sum<T, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a, c - a * PITCH + a,
+                                   c - a * PITCH - a);
+        orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
     }
     // general orbits: (+-a, +-b), (+-b, +-a), 0 < b < a
 #pragma unroll 1
     for (int a = 2; a < R; ++a) {
 #pragma unroll 1
         for (int b = 1; b < a && a * a + b * b < R * R; ++b, w += WS) {
-            float s0[2][T::C], s1[2][T::C];
-            quad_sum<T, PITCH, CHS>(s0, c + a * PITCH + b, c + a * PITCH - b, c - a * PITCH + b,
-                                    c - a * PITCH - b);
-            quad_sum<T, PITCH, CHS>(s1, c + b * PITCH + a, c + b * PITCH - a, c - b * PITCH + a,
-                                    c - b * PITCH - a);
-            float sum[2][T::C];
+            float s0[Q][T::C], s1[Q][T::C];
+            quad_sum<T, Q, PITCH, CHS>(s0, c + a * PITCH + b, c + a * PITCH - b, c - a * PITCH + b,
+                                       c - a * PITCH - b);
+            quad_sum<T, Q, PITCH, CHS>(s1, c + b * PITCH + a, c + b * PITCH - a, c - b * PITCH + a,
+                                       c - b * PITCH - a);
+            float sum[Q][T::C];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < Q; ++q)
 #pragma unroll
                 for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
-            orbit_fma<T, PITCH, CHS>(acc, sum, w);
+            orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
         }
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int s = 0; s < T::C; ++s)
 #pragma unroll
             for (int j = 0; j < T::KPS; ++j) u[q][T::kidx[s][j]] = acc[q][s][j];
 }
-
-
 
 // Gene diffusion, alpha mask, growth and update of one cell (gy, gx) given its
 // potentials u and its current state a[c]; writes A' and P' (and the saved
@@ -209,14 +204,19 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
     }
 }
 
+// Cells per thread: tiles of at most 256 cells give each thread one cell (for
+// small worlds, where parallelism is short), larger tiles a vertical pair.
 template <int TY, int TX>
-constexpr int step_threads() { return TY * TX / 2; }
+constexpr int step_cells_per_thread() { return (TY * TX <= 256) ? 1 : 2; }
+
+template <int TY, int TX>
+constexpr int step_threads() { return TY * TX / step_cells_per_thread<TY, TX>(); }
 
 
 template <class T, int R, int TY, int TX>
 constexpr int tile_lds_floats() { return T::C * (TY + 2 * R) * tile_pitch<R, TX>(); }
 
-// One tile of one world.  Each thread owns a vertical pair of cells.
+// One tile of one world.  Each thread owns Q vertically adjacent cells.
 template <class T, int R, int TY, int TX>
 __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA)
 {
@@ -225,6 +225,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     constexpr int CHS = PY * PITCH;
     constexpr int NK = T::NK;
     constexpr int NT = step_threads<TY, TX>();
+    constexpr int Q = step_cells_per_thread<TY, TX>();
 
     const int H = wd.H, W = wd.W;
     const size_t HW = (size_t)H * W;
@@ -274,17 +275,17 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     }
     __syncthreads();
 
-    // 2. potentials of the thread's two cells, 3. their epilogues
-    const int ly = 2 * (threadIdx.x / TX);
+    // 2. potentials of the thread's cells, 3. their epilogues
+    const int ly = Q * (threadIdx.x / TX);
     const int lx = threadIdx.x % TX;
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy >= H || gx >= W) return;
     const float* c = sA + (ly + R) * PITCH + (lx + R);
-    float u[2][NK];
-    conv_pair<T, R, PITCH, CHS>(c, (cfloat*)wd.wt, u);
+    float u[Q][NK];
+    conv_cells<T, Q, R, PITCH, CHS>(c, (cfloat*)wd.wt, u);
     if (mode == MODE_POTENTIALS) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < Q; ++q)
             if (gy + q < H) {
                 const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
 #pragma unroll
@@ -293,7 +294,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
         return;
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < Q; ++q) {
         if (gy + q < H) {
             float a[T::C];
 #pragma unroll
@@ -304,7 +305,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
 }
 
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
+__global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA);
@@ -343,7 +344,7 @@ epilogue_launch_fn find_epilogue_launcher(int table)
 
 // Persistent form: a fixed grid walks the (world, tile) work list.
 template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__((TY * TX / 2), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
+__global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
     // XCD-aware walk: the work list (tiles of a world in row order) is cut into
@@ -383,7 +384,7 @@ int batch_occupancy()
 {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batch_kernel<T, R, TY, TX>,
-                                                     TY * TX / 2, 0) != hipSuccess)
+                                                     step_threads<TY, TX>(), 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
@@ -402,9 +403,10 @@ struct Entry {
 static const Entry kEntries[] = {
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 32),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 32, 32),
-    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 32),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 64),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 64),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 8, 32),
+    LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 4, 64),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 16, 32),
     LENIA_ENTRY(Table3x15, TABLE_3x15, 13, 8, 32),
     LENIA_ENTRY(Table1x1, TABLE_1x1, 13, 16, 32),

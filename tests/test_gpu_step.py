@@ -98,7 +98,7 @@ def test_tiles_agree_bitwise(L):
     identical bits."""
     w = inputs.test_world(160, 192, seed=114, n_blobs=8)
     outs = []
-    for tile in [(16, 32), (32, 32), (8, 32), (16, 64), (8, 64)]:
+    for tile in [(16, 32), (32, 32), (8, 32), (16, 64), (8, 64), (4, 64)]:
         plan = L.Plan(w, tile=tile)
         assert (plan.info().tile_y, plan.info().tile_x) == tile
         outs.append(gpu_step(plan, w.A, w.P))
