@@ -49,97 +49,88 @@ struct BwdArgs {
 // ---------------------------------------------------------------------------
 // 1. per-cell pass
 // ---------------------------------------------------------------------------
+// One thread per (cell, target channel c): the 5 kernels updating channel c,
+// their 15 gene planes, the clip of z_c.  alpha comes from the saved mask.
 template <class T>
 __global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
 {
-    constexpr int NK = T::NK, NP = 3 * NK;
+    constexpr int NK = T::NK, KPD = T::KPD;
     const int H = b.H, W = b.W;
     const uint32_t HW = (uint32_t)H * (uint32_t)W;
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
     if (idx >= HW) return;
+    const int c = blockIdx.y;
     const int gy = (int)(idx / (uint32_t)W), gx = (int)(idx - (uint32_t)gy * W);
     const float eps = b.eps, dt = b.dt;
     const bool update = (b.mode == MODE_LOCAL_UPDATE);
     const bool alpha = update ? (b.alpha[idx] != 0) : true;
-
-    float a[T::C], zb[T::C];
-#pragma unroll
-    for (int c = 0; c < T::C; ++c) a[c] = (b.A + (size_t)c * HW)[idx];
+    const float a = (b.A + (size_t)c * HW)[idx];
+    const float g1 = (b.gA1 + (size_t)c * HW)[idx];
 
     if (!alpha) {
         // no growth: z = A, P' = 0.  ubar and numbar vanish here; the gather
         // pass masks them by alpha instead of reading stored zeros.
-#pragma unroll
-        for (int c = 0; c < T::C; ++c) {
-            const float g1 = (b.gA1 + (size_t)c * HW)[idx];
-            (b.gA + (size_t)c * HW)[idx] = (a[c] >= 0.f && a[c] <= 1.f) ? g1 : 0.f;
-        }
+        (b.gA + (size_t)c * HW)[idx] = (a >= 0.f && a <= 1.f) ? g1 : 0.f;
         return;
     }
+    int kk[KPD];
+#pragma unroll
+    for (int j = 0; j < KPD; ++j) kk[j] = T::kdst[c][j];
 
-    // genes at the cell: diffused (update) or as stored (read-only)
-    float pd[NP], rn[NP];
-    bool clip_ok[NP];
-    if (update) {
-        const Nbr nb = neighbours(gy, gx, H, W);
+    // genes of the channel's kernels: diffused (update) or as stored (read-only)
+    float pd[3][KPD], rn[3][KPD];
+    bool clip_ok[3][KPD];
+    const Nbr nb = neighbours(gy, gx, H, W);
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            const Diffused df = diffuse5(b.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
-            pd[q] = df.v;
-            const float inv = (df.n > 0) ? __builtin_amdgcn_rcpf((float)df.n) : 0.f;
-            const float qq = df.num * inv;
-            clip_ok[q] = (df.n > 0) && (qq >= 0.f) && (qq <= 1.f);
-            rn[q] = inv;
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int j = 0; j < KPD; ++j) {
+            const float* pl = b.P + (size_t)(p * NK + kk[j]) * HW;
+            if (update) {
+                const Diffused df = diffuse5(pl, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
+                pd[p][j] = df.v;
+                const float inv = (df.n > 0) ? __builtin_amdgcn_rcpf((float)df.n) : 0.f;
+                const float qq = df.num * inv;
+                clip_ok[p][j] = (df.n > 0) && (qq >= 0.f) && (qq <= 1.f);
+                rn[p][j] = inv;
+            } else {
+                pd[p][j] = pl[idx];
+                clip_ok[p][j] = true;
+                rn[p][j] = 1.f;
+            }
         }
-    } else {
+    float u[KPD];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) {
-            pd[q] = (b.P + (size_t)q * HW)[idx];
-            clip_ok[q] = true;
-            rn[q] = 1.f;
-        }
-    }
-    float u[NK];
-#pragma unroll
-    for (int k = 0; k < NK; ++k) u[k] = (b.U + (size_t)k * HW)[idx];
+    for (int j = 0; j < KPD; ++j) u[j] = (b.U + (size_t)kk[j] * HW)[idx];
 
-    // forward growth and pre-clip update (same arithmetic as the step kernel)
-    float sum[T::C];
+    // forward growth and pre-clip update (same arithmetic and order as the step
+    // kernel: ascending kernel index within the channel)
+    float sum = 0.f;
 #pragma unroll
-    for (int c = 0; c < T::C; ++c) sum[c] = 0.f;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
-#pragma unroll
-    for (int c = 0; c < T::C; ++c) {
-        const float z = a[c] + dt * sum[c];
-        const float g1 = (b.gA1 + (size_t)c * HW)[idx];
-        zb[c] = (z >= 0.f && z <= 1.f) ? g1 : 0.f;
-        (b.gA + (size_t)c * HW)[idx] = zb[c];
-    }
+    for (int j = 0; j < KPD; ++j) sum += growth(u[j], pd[0][j], pd[1][j], pd[2][j]);
+    const float z = a + dt * sum;
+    const float zb = (z >= 0.f && z <= 1.f) ? g1 : 0.f;
+    (b.gA + (size_t)c * HW)[idx] = zb;
+    const float gb = dt * zb;
     // growth derivatives
 #pragma unroll
-    for (int k = 0; k < NK; ++k) {
-        const float m = pd[k], s = pd[NK + k], h = pd[2 * NK + k];
-        const float d = u[k] - m;
+    for (int j = 0; j < KPD; ++j) {
+        const float m = pd[0][j], s = pd[1][j], h = pd[2][j];
+        const float d = u[j] - m;
         const float e = growth_bell(d, s);
-        const float gb = dt * zb[T::dst[k]];
         const float is2 = __builtin_amdgcn_rcpf(s * s);
         const float common = 2.f * h * e * d * is2;           // dg/dm
-        (b.ubar + (size_t)k * HW)[idx] = -gb * common;        // dg/du = -dg/dm
-        const float dm = gb * common;
-        const float ds = gb * common * d * __builtin_amdgcn_rcpf(s);
-        const float dh = gb * (2.f * e - 1.f);
-        const float gpm = b.gP1 ? (b.gP1 + (size_t)k * HW)[idx] : 0.f;
-        const float gps = b.gP1 ? (b.gP1 + (size_t)(NK + k) * HW)[idx] : 0.f;
-        const float gph = b.gP1 ? (b.gP1 + (size_t)(2 * NK + k) * HW)[idx] : 0.f;
-        const float pb[3] = {gpm + dm, gps + ds, gph + dh};
+        (b.ubar + (size_t)kk[j] * HW)[idx] = -gb * common;    // dg/du = -dg/dm
+        const float dd[3] = {gb * common, gb * common * d * __builtin_amdgcn_rcpf(s),
+                             gb * (2.f * e - 1.f)};
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            const int q = p * NK + k;
+            const size_t q = (size_t)(p * NK + kk[j]) * HW;
+            const float pb = (b.gP1 ? b.gP1[q + idx] : 0.f) + dd[p];
             if (update)
-                (b.numbar + (size_t)q * HW)[idx] = clip_ok[q] ? pb[p] * rn[q] : 0.f;
+                b.numbar[q + idx] = clip_ok[p][j] ? pb * rn[p][j] : 0.f;
             else
-                (b.gP + (size_t)q * HW)[idx] = pb[p];
+                b.gP[q + idx] = pb;
         }
     }
 }
@@ -377,7 +368,7 @@ template <class T, int R, int TY, int TX>
 hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipStream_t s)
 {
     const unsigned cells = (unsigned)a.H * (unsigned)a.W;
-    hipLaunchKernelGGL((bwd_cell_kernel<T>), dim3((cells + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((bwd_cell_kernel<T>), dim3((cells + 255) / 256, T::C), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX>), dim3(a.n_tiles, T::C),

@@ -64,8 +64,9 @@ inline int orbit_count(int R)
 // reading it ("slots"), and each kernel's target channel.
 // ---------------------------------------------------------------------------
 struct Table1x1 {
-    static constexpr int C = 1, NK = 1, KPS = 1;
+    static constexpr int C = 1, NK = 1, KPS = 1, KPD = 1;
     static constexpr int kidx[1][1] = {{0}};
+    static constexpr int kdst[1][1] = {{0}};     // kernels by target channel
     static constexpr int src[1] = {0};
     static constexpr int dst[1] = {0};
 };
@@ -73,8 +74,10 @@ struct Table1x1 {
 // 3 channels, 15 kernels: k = 0..8 self (channel k/3), k = 9..14 cross
 // (0->1, 0->2, 1->0, 1->2, 2->0, 2->1).
 struct Table3x15 {
-    static constexpr int C = 3, NK = 15, KPS = 5;
+    static constexpr int C = 3, NK = 15, KPS = 5, KPD = 5;
     static constexpr int kidx[3][5] = {{0, 1, 2, 9, 10}, {3, 4, 5, 11, 12}, {6, 7, 8, 13, 14}};
+    // kernels by target channel, ascending
+    static constexpr int kdst[3][5] = {{0, 1, 2, 11, 13}, {3, 4, 5, 9, 14}, {6, 7, 8, 10, 12}};
     static constexpr int src[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 2};
     static constexpr int dst[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 2, 0, 2, 0, 1};
 };

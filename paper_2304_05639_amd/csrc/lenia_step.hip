@@ -114,22 +114,30 @@ __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ 
                                    c - a * PITCH - a);
         orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
     }
-    // general orbits: (+-a, +-b), (+-b, +-a), 0 < b < a
+    // general orbits: (+-a, +-b), (+-b, +-a), 0 < b < a.  For each a the four
+    // base pointers (rows c +- a, columns c +- a) are formed once; the b loop is
+    // unrolled so that every tap is an immediate offset from one of them.
 #pragma unroll 1
     for (int a = 2; a < R; ++a) {
-#pragma unroll 1
-        for (int b = 1; b < a && a * a + b * b < R * R; ++b, w += WS) {
-            float s0[Q][T::C], s1[Q][T::C];
-            quad_sum<T, Q, PITCH, CHS>(s0, c + a * PITCH + b, c + a * PITCH - b, c - a * PITCH + b,
-                                       c - a * PITCH - b);
-            quad_sum<T, Q, PITCH, CHS>(s1, c + b * PITCH + a, c + b * PITCH - a, c - b * PITCH + a,
-                                       c - b * PITCH - a);
-            float sum[Q][T::C];
+        const float* rp = c + a * PITCH;
+        const float* rm = c - a * PITCH;
+        const float* cp = c + a;
+        const float* cm = c - a;
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
+        for (int b = 1; b < R - 1; ++b) {
+            if (b < a && a * a + b * b < R * R) {
+                float s0[Q][T::C], s1[Q][T::C];
+                quad_sum<T, Q, PITCH, CHS>(s0, rp + b, rp - b, rm + b, rm - b);
+                quad_sum<T, Q, PITCH, CHS>(s1, cp + b * PITCH, cm + b * PITCH, cp - b * PITCH,
+                                           cm - b * PITCH);
+                float sum[Q][T::C];
 #pragma unroll
-                for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
-            orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
+                orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
+                w += WS;
+            }
         }
     }
 #pragma unroll
@@ -167,20 +175,18 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
         for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
         float pd[NP];
         if (alpha) {
-            // diffusion of every gene plane over the r = 1 disk
+            // diffuse every gene plane (Section 2.3) and test it against the cutoff
             const Nbr nb = neighbours(gy, gx, H, W);
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const Diffused df =
-                    diffuse5(wd.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
+                const Diffused df = diffuse5(wd.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
                 pd[q] = df.v;
                 alpha = alpha && (df.v > eps);
             }
         }
         if (alpha) {
 #pragma unroll
-            for (int k = 0; k < NK; ++k)
-                sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+            for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) (wd.P_out + (size_t)q * HW)[oc] = alpha ? pd[q] : 0.f;
