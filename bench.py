@@ -74,16 +74,16 @@ def cpu_baseline(world, budget_s: float = 12.0):
                       f"convolution, OpenMP over rows), {dt:.1f} s"}
 
 
-def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3):
+def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3, conv: int = 1):
     """256^2 differentiable rollout (T = 64, checkpoint every 8, MSE to a
     random target): time of the backward pass (recomputing each segment with
     saved potentials, then the adjoint) over the forward pass (with checkpoint
-    saves), median of `reps`."""
+    saves), median of `reps`.  `conv` picks the forward's potential form."""
     import torch
     from paper_2304_05639_amd import inputs, lenia
     from paper_2304_05639_amd.autograd import rollout
     w = inputs.config5()
-    plan = lenia.Plan(w)
+    plan = lenia.Plan(w, conv=conv)
     A0 = torch.tensor(w.A, device="cuda", requires_grad=True)
     P0 = torch.tensor(w.P, device="cuda", requires_grad=True)
     beta = torch.tensor(w.beta, dtype=torch.float32, device="cuda", requires_grad=True)
@@ -105,6 +105,7 @@ def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3):
     fw, bw = sorted(fw[1:]), sorted(bw[1:])
     f, b = fw[len(fw) // 2], bw[len(bw) // 2]
     return {"value": b / f, "forward_ms": f, "backward_ms": b,
+            "conv": "dft_split_bf16" if conv == lenia.CONV_DFT_SPLIT_BF16 else "direct_f32",
             "workload": "256x256, 3 channels, 15 kernels, T=64, checkpoint every 8, MSE loss"}
 
 
@@ -207,7 +208,9 @@ def main():
     from paper_2304_05639_amd import inputs, lenia
 
     if args.only == "ratio":
-        print(json.dumps({"bwd_fwd_ratio": backward_forward_ratio()}), flush=True)
+        print(json.dumps({"bwd_fwd_ratio": backward_forward_ratio(),
+                          "bwd_fwd_ratio_dft": backward_forward_ratio(
+                              conv=lenia.CONV_DFT_SPLIT_BF16)}), flush=True)
         return
     if args.only == "batched":
         print(json.dumps({"batched": batched_throughput()}), flush=True)
@@ -280,6 +283,8 @@ def main():
         del src, dst
     if not args.no_backward:
         out["bwd_fwd_ratio"] = backward_forward_ratio()
+        if not args.no_dft:
+            out["bwd_fwd_ratio_dft"] = backward_forward_ratio(conv=lenia.CONV_DFT_SPLIT_BF16)
     if args.batched:
         out["batched"] = batched_throughput()
     if not args.no_cpu_baseline:

@@ -74,7 +74,8 @@ typedef enum {
 /* Descriptor of one world.  All pointers are host pointers read only during
  * lenia_plan / lenia_plan_batched / lenia_desc_validate. */
 typedef struct {
-    int32_t H, W;               /* torus rows, columns (>= 1)                    */
+    int32_t H, W;               /* torus rows, columns: each in [1, 65536] and   */
+                                /* H * W < 2^30 (a plane below 4 GiB)            */
     int32_t n_channels;         /* C: 1 or 3                                     */
     int32_t n_kernels;          /* NK: 1 (with C = 1) or 15 (with C = 3)         */
     const int32_t* src;         /* [NK] source channel of each kernel            */
@@ -89,7 +90,8 @@ typedef struct {
     const double* m;            /* [NK] global genes, used iff localized == 0    */
     const double* s;            /*      (s > 0)                                  */
     const double* h;
-    double eps;                 /* mask cutoff (0.01), in [0, 1)                 */
+    double eps;                 /* mask cutoff (0.01), in [0, 1); >= 2^-64 when  */
+                                /* genotype_update is set                        */
     int32_t r_diff;             /* diffusion disk radius (1)                     */
     int32_t conv;               /* lenia_conv                                    */
     int32_t tile_y, tile_x;     /* output tile of the fused step kernel; 0,0 =

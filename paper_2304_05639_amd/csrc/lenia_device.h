@@ -24,6 +24,26 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb)
 
 __device__ __forceinline__ float clip01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }
 
+// Raw buffer access to one plane: a descriptor (base address, size in bytes)
+// held in scalar registers plus a 32-bit byte offset per lane, from which the
+// memory unit forms the address.  An access past the plane's end reads 0 and a
+// store there is dropped.  A plane is below 4 GiB.
+typedef __amdgpu_buffer_rsrc_t plane_t;
+
+__device__ __forceinline__ plane_t plane(const float* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes,
+                                            0x00020000);
+}
+__device__ __forceinline__ float pld(plane_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void pst(plane_t r, uint32_t off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+}
+
 // Gaussian factor e = exp(-(u-m)^2 / (2 s^2)) of the growth mapping, with the
 // hardware reciprocal and exponential (a few ulp; the exponent's error only
 // matters where e is far below the state tolerance).
@@ -72,6 +92,9 @@ __device__ __forceinline__ void stage_planes(float* dst, const float* const (&sr
     constexpr int NG = PY * PX;
     constexpr int IT = (NG + NT - 1) / NT;
     const bool single_wrap = (H >= TY + R) && (W >= TX + R);
+    plane_t pl[NPL];
+#pragma unroll
+    for (int p = 0; p < NPL; ++p) pl[p] = plane(src[p], 4u * (uint32_t)H * (uint32_t)W);
     float v[IT][NPL];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -84,7 +107,7 @@ __device__ __forceinline__ void stage_planes(float* dst, const float* const (&sr
             const uint32_t o = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
             const bool keep = (NM == 0) || (mask[o] != 0);
 #pragma unroll
-            for (int p = 0; p < NPL; ++p) v[it][p] = (p < NM && !keep) ? 0.f : src[p][o];
+            for (int p = 0; p < NPL; ++p) v[it][p] = (p < NM && !keep) ? 0.f : pld(pl[p], 4u * o);
         }
     }
 #pragma unroll
@@ -121,6 +144,45 @@ __device__ __forceinline__ Diffused diffuse5(const float* pl, uint32_t ou, uint3
     r.n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
     r.v = (r.n > 0) ? clip01(r.num * __builtin_amdgcn_rcpf((float)r.n)) : 0.f;
     return r;
+}
+
+// Diffusion of one plane with byte offsets of the 5 disk cells (as diffuse5,
+// same summation order and result).  The count of values above eps is taken
+// as sum_i clamp(cs * v_i + ncs) with cs = 2^100 and ncs = -cs * eps, one FMA
+// per value: the product is exact and the FMA rounds once, so the term has
+// the sign of v_i - eps; for eps >= 2^-64, v_i > eps means v_i - eps >=
+// ulp(eps) >= 2^-87 and the clamped term is exactly 1, while v_i <= eps gives 0.
+struct NbrB {
+    uint32_t c, u, d, l, r;
+};
+
+__device__ __forceinline__ float diffuse5b(plane_t pl, const NbrB& o, float cs, float ncs)
+{
+    const float vu = pld(pl, o.u), vl = pld(pl, o.l), vc = pld(pl, o.c), vr = pld(pl, o.r),
+                vd = pld(pl, o.d);
+    const float num = (((vu + vl) + vc) + vr) + vd;
+    const float n = clip01(fmaf(vu, cs, ncs)) + clip01(fmaf(vl, cs, ncs)) +
+                    clip01(fmaf(vc, cs, ncs)) + clip01(fmaf(vr, cs, ncs)) +
+                    clip01(fmaf(vd, cs, ncs));
+    // evaluated unconditionally (n = 0 gives inf or NaN, which the select drops)
+    const float v = clip01(num * __builtin_amdgcn_rcpf(n));
+    return (n > 0.f) ? v : 0.f;
+}
+
+__device__ __forceinline__ NbrB neighbour_bytes(int gy, int gx, int H, int W)
+{
+    const int ym = (gy == 0) ? H - 1 : gy - 1;
+    const int yp = (gy == H - 1) ? 0 : gy + 1;
+    const int xm = (gx == 0) ? W - 1 : gx - 1;
+    const int xp = (gx == W - 1) ? 0 : gx + 1;
+    const uint32_t row = (uint32_t)gy * (uint32_t)W;
+    NbrB n;
+    n.c = 4u * (row + gx);
+    n.u = 4u * ((uint32_t)ym * (uint32_t)W + gx);
+    n.d = 4u * ((uint32_t)yp * (uint32_t)W + gx);
+    n.l = 4u * (row + xm);
+    n.r = 4u * (row + xp);
+    return n;
 }
 
 // 32-bit in-plane offsets of a cell and its 4 torus neighbours.

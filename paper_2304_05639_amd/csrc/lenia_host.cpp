@@ -121,6 +121,8 @@ lenia_status validate(const lenia_desc* d)
     if (!d) return fail(LENIA_ERR_INVALID_ARG, "descriptor is NULL");
     if (d->H < 1 || d->W < 1 || d->H > 65536 || d->W > 65536)
         return fail(LENIA_ERR_INVALID_ARG, "H and W must be in [1, 65536]");
+    if ((int64_t)d->H * d->W >= ((int64_t)1 << 30))
+        return fail(LENIA_ERR_INVALID_ARG, "H * W must be below 2^30 (a plane below 4 GiB)");
     if (d->n_channels < 1 || d->n_channels > LENIA_MAX_CHANNELS)
         return fail(LENIA_ERR_INVALID_ARG, "n_channels must be in [1, 3]");
     if (d->n_kernels < 1 || d->n_kernels > LENIA_MAX_KERNELS)
@@ -161,6 +163,8 @@ lenia_status validate(const lenia_desc* d)
     }
     if (!finite(d->eps) || d->eps < 0.0 || d->eps >= 1.0)
         return fail(LENIA_ERR_INVALID_ARG, "eps must be in [0, 1)");
+    if (d->genotype_update && d->eps < 0x1p-64)
+        return fail(LENIA_ERR_INVALID_ARG, "eps must be >= 2^-64 with genotype_update");
     if (d->genotype_update && d->r_diff < 0)
         return fail(LENIA_ERR_INVALID_ARG, "r_diff must be >= 0");
     if (d->conv < LENIA_CONV_AUTO || d->conv > LENIA_CONV_DFT_SPLIT_F16)

@@ -104,6 +104,8 @@ struct WorldArgs {
     float dt;
     float eps;             // the largest float <= the descriptor's eps, so that
                            // (float x > eps) == ((double)x > eps_double)
+    float cnt_scale;       // 2^100: threshold count by FMA + clamp (needs eps >= 2^-64)
+    float cnt_bias;        // -cnt_scale * eps (exact)
     float gm[kMaxK], gs[kMaxK], gh[kMaxK];   // global genes (MODE_GLOBAL)
 };
 

@@ -33,6 +33,8 @@ WorldArgs WorldPlan::args_template() const
     a.W = W;
     a.dt = (float)dt;
     a.eps = eps_below(eps);
+    a.cnt_scale = std::ldexp(1.0f, 100);
+    a.cnt_bias = -a.cnt_scale * a.eps;
     for (int k = 0; k < NK && k < kMaxK; ++k) {
         if (!gm.empty()) {
             a.gm[k] = (float)gm[k];

@@ -159,9 +159,10 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
     constexpr int NP = 3 * NK;
     const int H = wd.H, W = wd.W;
     const size_t HW = (size_t)H * W;
-    // in-plane offsets fit 32 bits (H, W <= 65536 and a plane < 2^32 bytes is
-    // required); plane bases are uniform, so loads use a scalar base
-    const uint32_t oc = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+    // byte offsets within a plane fit 32 bits (a plane is below 4 GiB); every
+    // plane is accessed through a scalar buffer descriptor
+    const uint32_t ob = 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx);
+    const uint32_t pb = 4u * (uint32_t)HW;
     const float eps = wd.eps;
     float sum[T::C];
 #pragma unroll
@@ -176,12 +177,12 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
         float pd[NP];
         if (alpha) {
             // diffuse every gene plane (Section 2.3) and test it against the cutoff
-            const Nbr nb = neighbours(gy, gx, H, W);
+            const NbrB nb = neighbour_bytes(gy, gx, H, W);
+            const float cs = wd.cnt_scale, ncs = wd.cnt_bias;
 #pragma unroll
             for (int q = 0; q < NP; ++q) {
-                const Diffused df = diffuse5(wd.P + (size_t)q * HW, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
-                pd[q] = df.v;
-                alpha = alpha && (df.v > eps);
+                pd[q] = diffuse5b(plane(wd.P + (size_t)q * HW, pb), nb, cs, ncs);
+                alpha = alpha && (pd[q] > eps);
             }
         }
         if (alpha) {
@@ -189,24 +190,26 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
             for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
         }
 #pragma unroll
-        for (int q = 0; q < NP; ++q) (wd.P_out + (size_t)q * HW)[oc] = alpha ? pd[q] : 0.f;
-        if (wd.alpha_save) wd.alpha_save[oc] = alpha ? 1 : 0;
+        for (int q = 0; q < NP; ++q) pst(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
+        if (wd.alpha_save) wd.alpha_save[ob >> 2] = alpha ? 1 : 0;
     } else if (mode == MODE_LOCAL_READONLY) {
 #pragma unroll
         for (int k = 0; k < NK; ++k)
-            sum[T::dst[k]] += growth(u[k], wd.P[(size_t)k * HW + oc], wd.P[(size_t)(NK + k) * HW + oc],
-                                     wd.P[(size_t)(2 * NK + k) * HW + oc]);
-        if (wd.alpha_save) wd.alpha_save[oc] = 1;
+            sum[T::dst[k]] += growth(u[k], pld(plane(wd.P + (size_t)k * HW, pb), ob),
+                                     pld(plane(wd.P + (size_t)(NK + k) * HW, pb), ob),
+                                     pld(plane(wd.P + (size_t)(2 * NK + k) * HW, pb), ob));
+        if (wd.alpha_save) wd.alpha_save[ob >> 2] = 1;
     } else {
 #pragma unroll
         for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], wd.gm[k], wd.gs[k], wd.gh[k]);
-        if (wd.alpha_save) wd.alpha_save[oc] = 1;
+        if (wd.alpha_save) wd.alpha_save[ob >> 2] = 1;
     }
 #pragma unroll
-    for (int c = 0; c < T::C; ++c) (wd.A_out + (size_t)c * HW)[oc] = clip01(a[c] + wd.dt * sum[c]);
+    for (int c = 0; c < T::C; ++c)
+        pst(plane(wd.A_out + (size_t)c * HW, pb), ob, clip01(a[c] + wd.dt * sum[c]));
     if (wd.U_save) {
 #pragma unroll
-        for (int k = 0; k < NK; ++k) (wd.U_save + (size_t)k * HW)[oc] = u[k];
+        for (int k = 0; k < NK; ++k) pst(plane(wd.U_save + (size_t)k * HW, pb), ob, u[k]);
     }
 }
 

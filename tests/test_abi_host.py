@@ -53,7 +53,8 @@ def _mut(w, **changes):
     dict(eps=-0.1), dict(localized=2), dict(genotype_update=3),
     dict(n_shells=np.array([0] * 15, np.int32)), dict(n_shells=np.array([4] * 15, np.int32)),
     dict(beta=np.zeros((15, 3))), dict(beta=np.full((15, 3), -1.0)),
-    dict(src=tuple([5] * 15)), dict(R=0), dict(r_diff=-1),
+    dict(src=tuple([5] * 15)), dict(R=0), dict(r_diff=-1), dict(H=65536, W=32768),
+    dict(eps=0.0), dict(eps=1e-30),
 ])
 def test_invalid_descriptors(changes):
     w = _mut(inputs.test_world(32, 32, seed=2, n_blobs=1), **changes)

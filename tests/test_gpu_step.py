@@ -172,30 +172,50 @@ def test_call_errors(L):
         plan.step(A[:2], P)
 
 
-def test_full_size_sampled_windows(L, oracle):
+@pytest.fixture(scope="module")
+def c3_world():
+    return inputs.config3()
+
+
+@pytest.mark.parametrize("t0", [0, 100, 1000])
+def test_full_size_sampled_windows(L, oracle, c3_world, t0):
     """4096^2, 2000 blobs with their own genotypes, in the benchmark's launch
-    configuration: sampled windows (including ones across the torus seam)
+    configuration.  The GPU runs t0 steps freely; one more step is then taken
+    from that state (teacher forcing: the oracle starts from the same FP32
+    snapshot) and sampled windows, including ones across the torus seam, are
     checked cell by cell against the oracle run on the window plus its halo."""
     import torch
-    w = inputs.config3()
+    w = c3_world
     plan = L.Plan(w)
     A, P = dev(w.A), dev(w.P)
+    if t0:
+        A, P = plan.step(A, P, n_steps=t0)
+    torch.cuda.synchronize()
+    A0h, P0h = host(A), host(P)
     A1, P1 = plan.step(A, P)
     torch.cuda.synchronize()
     A1h, P1h = host(A1), host(P1)
     del A, P, A1, P1
-    rng = np.random.default_rng(5)
+    rng = np.random.default_rng(5 + t0)
     m = w.R + 1                          # halo: kernel radius + diffusion radius
     hw = 48
     starts = [(0, 0), (4096 - 20, 4096 - 30), (2048, 17)] + \
              [tuple(rng.integers(0, 4096, 2)) for _ in range(3)]
+    # one window centred on the densest matter, so that it is never all empty
+    dens = A0h.sum(0)[::64, ::64]
+    iy, ix = np.unravel_index(int(dens.argmax()), dens.shape)
+    starts.append((iy * 64, ix * 64))
+    active = 0
     for (y0, x0) in starts:
-        Aw = window(w.A, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
-        Pw = window(w.P, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
+        Aw = window(A0h, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
+        Pw = window(P0h, y0 - m, x0 - m, hw + 2 * m, hw + 2 * m)
         dw = oracle.Desc(hw + 2 * m, hw + 2 * m, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta,
                          w.dt, 1, 1)
         r = oracle.step(dw, Aw, Pw)
         inner = (slice(m, m + hw), slice(m, m + hw))
         rr = dict(A=r["A"][(slice(None),) + inner], P=r["P"][(slice(None), slice(None)) + inner],
                   amb=r["amb"][inner])
+        active += int((r["alpha"][inner] == 1).sum())
         compare_step(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw))
+    print(f"4096^2 at t={t0}: {len(starts)} windows, {active} cells with alpha = 1")
+    assert active > 0
