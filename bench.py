@@ -22,29 +22,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = 384        # read A 12 + write A 12 + read P 180 + write P 180 (FP32)
-STEP_SRCS = [os.path.join(ROOT, "paper_2304_05639_amd", "csrc", f)
-             for f in ("lenia_step.hip", "lenia_device.h", "lenia_internal.h")]
+CSRC = os.path.join(ROOT, "paper_2304_05639_amd", "csrc")
+STEP_SRCS = [os.path.join(CSRC, f) for f in ("lenia_step.hip", "lenia_device.h", "lenia_internal.h")]
+DFT_SRCS = [os.path.join(CSRC, f) for f in ("lenia_dft.hip", "lenia_device.h", "lenia_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_4096.json")
+DFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dft_conv_4096.json")
 
 
-def kernel_sha() -> str:
-    """Hash of the step kernel's sources (counters are only valid for them)."""
+def kernel_sha(srcs=STEP_SRCS) -> str:
+    """Hash of a kernel's sources (counters are only valid for them)."""
     h = hashlib.sha256()
-    for fn in STEP_SRCS:
+    for fn in srcs:
         with open(fn, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if absent or taken on another version of the step kernel."""
+def measured_traffic(cells: int, path: str = TRAFFIC_FILE, srcs=STEP_SRCS):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None if absent or taken on another version of the kernel."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("cells") != cells:
+    if t.get("kernel_sha") != kernel_sha(srcs) or t.get("cells") != cells:
         return None
     return t.get("bytes_per_launch")
 
@@ -111,7 +113,8 @@ def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3, conv
 
 def batched_throughput(steps: int = 20, warmup: int = 2):
     """256 independent worlds of sides 128..1024 stepped together in one
-    persistent launch per step (graph replay): cell-updates/s over all worlds."""
+    launch per step over the (world, tile) work list (graph replay): cell-updates/s
+    over all worlds."""
     import torch
     from paper_2304_05639_amd import inputs, lenia
     worlds = inputs.config4()
@@ -174,7 +177,8 @@ def dft_form(world, steps: int = 20, warmup: int = 2):
             "ms_per_step": s_ms, "mfma_kernel_ms": k_ms,
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
-                         "traffic": None},
+                         "traffic": measured_traffic(world.H * world.W, DFT_TRAFFIC_FILE,
+                                                     DFT_SRCS)},
             "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile"}
 
 
