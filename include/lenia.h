@@ -149,7 +149,7 @@ LENIA_API lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float
 
 /* Advances every world of a batched plan by n_steps, in place: A[i], P[i] are
  * device pointers of world i (host arrays of n_worlds pointers).  The steps
- * run as one persistent launch per step over a (world, tile) work list,
+ * run as one launch per step over a (world, tile) work list,
  * captured once into a HIP graph per pointer set and replayed. */
 LENIA_API lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P,
                                 int32_t n_steps, void* stream);

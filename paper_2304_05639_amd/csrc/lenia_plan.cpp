@@ -342,7 +342,7 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
                         e = hipMemcpy(ditems, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
                     if (e == hipSuccess) {
                         BatchList bl{dtab, ditems, (int)items.size()};
-                        e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, p->grid, s);
+                        e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, (int)items.size(), s);
                     }
                     if (e == hipSuccess) e = hipStreamSynchronize(s);
                     (void)hipFree(dtab);
@@ -405,14 +405,6 @@ static lenia_status finish_tile_choice(lenia_plan_t p, const lenia_desc* d, hipS
     return LENIA_OK;
 }
 
-static int device_cus(int dev)
-{
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-        return prop.multiProcessorCount;
-    return 256;
-}
-
 }  // namespace lenia
 
 // ---------------------------------------------------------------------------
@@ -451,7 +443,6 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     if (st == LENIA_OK && p->conv == LENIA_CONV_DFT_SPLIT_BF16)
         st = build_dft_tables(p, p->worlds[0], s, keep);
     if (st == LENIA_OK && batched) {
-        p->grid = 2 * device_cus(p->device);
         for (int ph = 0; ph < 2 && st == LENIA_OK; ++ph) {
             void* q = nullptr;
             st = [&] {
@@ -465,8 +456,6 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     }
     if (st == LENIA_OK) st = finish_tile_choice(p, &ds[0], s);
     if (st == LENIA_OK && batched) {
-        // persistent grid: as many workgroups as fit on the device at once
-        p->grid = batch_blocks_per_cu(p->table, p->R, p->tile_y, p->tile_x) * device_cus(p->device);
         std::vector<int2> items;
         for (int i = 0; i < n; ++i) {
             const WorldPlan& w = p->worlds[i];
@@ -474,6 +463,9 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
             for (int t = 0; t < nt; ++t) items.push_back(make_int2(i, t));
         }
         p->n_items = (int)items.size();
+        // one workgroup per work item: the hardware dispatcher balances tiles
+        // of uneven cost (active vs empty regions) across the CUs
+        p->grid = p->n_items;
         void* q = nullptr;
         hipError_t e = hipMalloc(&q, items.size() * sizeof(int2));
         if (e != hipSuccess) {
@@ -727,7 +719,7 @@ lenia_status fill_batch_tables(lenia_plan_t p, float* const* A, float* const* P,
 
 extern "C" {
 
-// Batched steps: one persistent launch per step; a pair of steps (phase 0 then
+// Batched steps: one launch per step over the work list; a pair of steps (phase 0 then
 // phase 1) is captured into a HIP graph once per pointer set and replayed.
 lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P, int32_t n_steps,
                                 void* stream)

@@ -351,7 +351,9 @@ epilogue_launch_fn find_epilogue_launcher(int table)
     return (table == TABLE_3x15) ? &launch_epilogue<Table3x15> : &launch_epilogue<Table1x1>;
 }
 
-// Persistent form: a fixed grid walks the (world, tile) work list.
+// Batched form: the grid walks the (world, tile) work list.  It is launched
+// with one workgroup per item, so that the hardware dispatcher balances tiles
+// of uneven cost; a smaller grid strides over the list.
 template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
@@ -387,27 +389,14 @@ hipError_t launch_batch(const BatchList& b, int mode, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-// Workgroups of the persistent kernel that fit on one CU at once.
-template <class T, int R, int TY, int TX>
-int batch_occupancy()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_batch_kernel<T, R, TY, TX>,
-                                                     step_threads<TY, TX>(), 0) != hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
-}
-
 struct Entry {
     int table, R, ty, tx;
     step_launch_fn step;
     batch_launch_fn batch;
-    int (*occupancy)();
 };
 
 #define LENIA_ENTRY(TB, TID, RR, TYY, TXX)                                                   \
-    {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>, \
-     &batch_occupancy<TB, RR, TYY, TXX>}
+    {TID, RR, TYY, TXX, &launch_step<TB, RR, TYY, TXX>, &launch_batch<TB, RR, TYY, TXX>}
 
 static const Entry kEntries[] = {
     LENIA_ENTRY(Table3x15, TABLE_3x15, 12, 16, 32),
@@ -436,13 +425,6 @@ batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx)
     for (const Entry& e : kEntries)
         if (e.table == table && e.R == R && e.ty == ty && e.tx == tx) return e.batch;
     return nullptr;
-}
-
-int batch_blocks_per_cu(int table, int R, int ty, int tx)
-{
-    for (const Entry& e : kEntries)
-        if (e.table == table && e.R == R && e.ty == ty && e.tx == tx) return e.occupancy();
-    return 1;
 }
 
 int step_tile_candidates(int table, int R, int* ty, int* tx, int max)

@@ -1,5 +1,5 @@
 """Batched worlds of uneven sizes (lenia_plan_batched / lenia_step_batched,
-one persistent launch per step replayed from a HIP graph): every world of a
+one launch per step over the work list, replayed from a HIP graph): every world of a
 batch must equal the same world stepped alone with the same tile, bit for bit,
 and one world checked against the FP64 oracle."""
 import os
