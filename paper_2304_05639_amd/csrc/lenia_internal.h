@@ -106,6 +106,8 @@ struct WorldArgs {
                            // (float x > eps) == ((double)x > eps_double)
     float cnt_scale;       // 2^100: threshold count by FMA + clamp (needs eps >= 2^-64)
     float cnt_bias;        // -cnt_scale * eps (exact)
+    float skip_thr;        // eps * (1 - 2^-10), rounded down: a tile whose window of one
+                           // source channel stays <= skip_thr has alpha = 0 everywhere
     float gm[kMaxK], gs[kMaxK], gh[kMaxK];   // global genes (MODE_GLOBAL)
 };
 

@@ -35,6 +35,12 @@ WorldArgs WorldPlan::args_template() const
     a.eps = eps_below(eps);
     a.cnt_scale = std::ldexp(1.0f, 100);
     a.cnt_bias = -a.cnt_scale * a.eps;
+    {
+        const double t = (double)a.eps * (1.0 - 1.0 / 1024.0);
+        float f = (float)t;
+        if ((double)f > t) f = std::nextafter(f, -1.0f);
+        a.skip_thr = f;
+    }
     for (int k = 0; k < NK && k < kMaxK; ++k) {
         if (!gm.empty()) {
             a.gm[k] = (float)gm[k];

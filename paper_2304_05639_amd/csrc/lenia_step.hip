@@ -227,7 +227,8 @@ constexpr int tile_lds_floats() { return T::C * (TY + 2 * R) * tile_pitch<R, TX>
 
 // One tile of one world.  Each thread owns Q vertically adjacent cells.
 template <class T, int R, int TY, int TX>
-__device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA)
+__device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA,
+                                             int* tile_flag)
 {
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
     constexpr int PITCH = tile_pitch<R, TX>();
@@ -241,6 +242,16 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int tyi = tile / wd.tiles_x;
     const int txi = tile - tyi * wd.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
+
+    // An empty tile: the potentials u_k are averages (non-negative weights
+    // summing to 1) of their source channel over the window, so if some
+    // channel's window stays <= skip_thr < eps, every u_k reading it is below
+    // the cutoff and alpha = 0 on the whole tile (Section 2.2).  Then
+    // A' = clip01(A) and P' = 0 exactly, without the convolution.  Decided
+    // only where the potentials are not requested.
+    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
+    if (may_skip && threadIdx.x == 0) *tile_flag = 0;
+    int wave_bits = 0;   // bit c: some window value of channel c above skip_thr
 
     // 1. stage A (+halo, wrapped) with all of a thread's loads in flight at once;
     // the index arithmetic of a halo position is shared by the channels
@@ -281,8 +292,43 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
                 for (int ch = 0; ch < T::C; ++ch) sA[ch * CHS + yy * PITCH + xx] = v[it][ch];
             }
         }
+        if (may_skip) {
+#pragma unroll
+            for (int ch = 0; ch < T::C; ++ch) {
+                bool above = false;
+#pragma unroll
+                for (int it = 0; it < IT; ++it)
+                    above = above || ((threadIdx.x + it * NT < NG) && (v[it][ch] > wd.skip_thr));
+                wave_bits |= (__ballot(above) != 0ull) ? (1 << ch) : 0;
+            }
+        }
     }
     __syncthreads();
+    if (may_skip) {
+        if ((threadIdx.x & 63) == 0 && wave_bits != 0) atomicOr(tile_flag, wave_bits);
+        __syncthreads();
+        if (*tile_flag != (1 << T::C) - 1) {
+            // some channel is empty on the window: alpha = 0 on the tile
+            const int ly = Q * (threadIdx.x / TX);
+            const int lx = threadIdx.x % TX;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int gy = y0 + ly + q, gx = x0 + lx;
+                if (gy < H && gx < W) {
+                    const uint32_t ob = 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx);
+                    const uint32_t pb = 4u * (uint32_t)HW;
+                    const float* c = sA + (ly + q + R) * PITCH + (lx + R);
+#pragma unroll
+                    for (int ch = 0; ch < T::C; ++ch)
+                        pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(c[ch * CHS]));
+#pragma unroll
+                    for (int p = 0; p < 3 * NK; ++p) pst(plane(wd.P_out + (size_t)p * HW, pb), ob, 0.f);
+                    if (wd.alpha_save) wd.alpha_save[ob >> 2] = 0;
+                }
+            }
+            return;
+        }
+    }
 
     // 2. potentials of the thread's cells, 3. their epilogues
     const int ly = Q * (threadIdx.x / TX);
@@ -317,7 +363,8 @@ template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
-    process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA);
+    __shared__ int tile_flag;
+    process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA, &tile_flag);
 }
 
 // Epilogue of a step whose potentials were computed elsewhere (the MFMA DFT
@@ -358,6 +405,7 @@ template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
+    __shared__ int tile_flag;
     // XCD-aware walk: the work list (tiles of a world in row order) is cut into
     // 8 contiguous chunks, one per XCD, so that neighbouring tiles, whose halos
     // overlap, are processed by workgroups sharing an L2
@@ -368,7 +416,7 @@ __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void ste
     const int end = min(bl.n_items, begin + chunk);
     for (int i = begin + slot; i < end; i += per_xcd) {
         const int2 it = bl.items[i];
-        process_tile<T, R, TY, TX>(bl.worlds[it.x], it.y, mode, sA);
+        process_tile<T, R, TY, TX>(bl.worlds[it.x], it.y, mode, sA, &tile_flag);
         __syncthreads();   // LDS reuse by the next item
     }
 }

@@ -106,6 +106,21 @@ def test_tiles_agree_bitwise(L):
         assert np.array_equal(A1, outs[0][0]) and np.array_equal(P1, outs[0][1])
 
 
+@pytest.mark.parametrize("tile", [(8, 32), (16, 32)])
+def test_empty_tile_shortcut_bitwise(L, tile):
+    """Tiles where some channel is empty over the whole window (tile + halo)
+    have alpha = 0 everywhere, so the step skips their convolution.  Asking
+    for the saved potentials turns the shortcut off; both must give identical
+    bits, on a world with empty and occupied tiles."""
+    w = inputs.test_world(256, 320, seed=116, n_blobs=4)
+    assert (w.A == 0).all(axis=0).mean() > 0.5          # mostly empty space
+    plan = L.Plan(w, tile=tile)
+    a1, p1 = gpu_step(plan, w.A, w.P)
+    a2, p2 = gpu_step(plan, w.A, w.P, saved=plan.new_saved())
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    assert (p1 != 0).any() and (a1 != 0).any()
+
+
 def test_translation_bitwise(L):
     w = inputs.test_world(96, 128, seed=115, n_blobs=5)
     plan = L.Plan(w)
