@@ -11,15 +11,22 @@ namespace lenia {
 // VALU instructions as SGPR operands.
 typedef const __attribute__((address_space(4))) float cfloat;
 
-// Block id -> tile id such that consecutive tiles land on the same XCD (the
-// dispatcher deals workgroups round-robin over the 8 XCDs, each with its own
-// L2): XCD x receives a contiguous band of tile rows, so halo re-reads of
-// neighbouring tiles hit that XCD's L2.
+// Block id -> tile id.  The dispatcher deals workgroups round-robin over the
+// 8 XCDs (block b runs on XCD b & 7), each XCD with its own L2.  Tiles are
+// grouped into runs of kTileRun consecutive tiles and run r goes to XCD r & 7:
+// the tiles of a run share an L2, so their overlapping halos are re-read from
+// it, and every XCD gets runs from all over the tile list, so regions of
+// uneven cost (active creatures, empty space) are spread evenly.  Tiles past
+// the last whole group of 8 runs map to themselves.
+constexpr int kTileRun = 512;
+
 __device__ __forceinline__ int xcd_tile(int bid, int nb)
 {
-    const int q = nb >> 3, r = nb & 7;
-    const int xcd = bid & 7, slot = bid >> 3;
-    return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    const int full = (nb / (8 * kTileRun)) * (8 * kTileRun);
+    if (bid >= full) return bid;
+    const int xcd = bid & 7, k = bid >> 3;
+    const int run = (k / kTileRun) * 8 + xcd;
+    return run * kTileRun + (k % kTileRun);
 }
 
 __device__ __forceinline__ float clip01(float x) { return fminf(fmaxf(x, 0.f), 1.f); }

@@ -120,7 +120,8 @@ struct BatchList {
 
 // Launchers (defined in lenia_step.hip).  Return hipSuccess or the launch error.
 typedef hipError_t (*step_launch_fn)(const WorldArgs& w, int mode, hipStream_t s);
-typedef hipError_t (*batch_launch_fn)(const BatchList& b, int mode, int grid, hipStream_t s);
+// one workgroup per work item (grid = b.n_items)
+typedef hipError_t (*batch_launch_fn)(const BatchList& b, int mode, hipStream_t s);
 
 step_launch_fn find_step_launcher(int table, int R, int ty, int tx);
 batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx);

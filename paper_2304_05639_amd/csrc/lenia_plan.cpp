@@ -348,7 +348,7 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
                         e = hipMemcpy(ditems, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
                     if (e == hipSuccess) {
                         BatchList bl{dtab, ditems, (int)items.size()};
-                        e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, (int)items.size(), s);
+                        e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, s);
                     }
                     if (e == hipSuccess) e = hipStreamSynchronize(s);
                     (void)hipFree(dtab);
@@ -469,9 +469,6 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
             for (int t = 0; t < nt; ++t) items.push_back(make_int2(i, t));
         }
         p->n_items = (int)items.size();
-        // one workgroup per work item: the hardware dispatcher balances tiles
-        // of uneven cost (active vs empty regions) across the CUs
-        p->grid = p->n_items;
         void* q = nullptr;
         hipError_t e = hipMalloc(&q, items.size() * sizeof(int2));
         if (e != hipSuccess) {
@@ -769,8 +766,8 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
             if (e == hipSuccess) {
                 BatchList b0{p->d_tables[0], p->d_items, p->n_items};
                 BatchList b1{p->d_tables[1], p->d_items, p->n_items};
-                hipError_t le = p->batch_fn(b0, p->mode, p->grid, cs);
-                if (le == hipSuccess) le = p->batch_fn(b1, p->mode, p->grid, cs);
+                hipError_t le = p->batch_fn(b0, p->mode, cs);
+                if (le == hipSuccess) le = p->batch_fn(b1, p->mode, cs);
                 e = hipStreamEndCapture(cs, &g);
                 if (e == hipSuccess) e = le;
             }
@@ -787,7 +784,7 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
         if (e == hipSuccess && (n_steps % 2 == 1)) {
             // last step: caller -> workspace, then copy back
             BatchList b0{p->d_tables[0], p->d_items, p->n_items};
-            e = p->batch_fn(b0, p->mode, p->grid, s);
+            e = p->batch_fn(b0, p->mode, s);
             for (int i = 0; i < n && e == hipSuccess; ++i) {
                 WorldPlan& w = p->worlds[i];
                 e = hipMemcpyAsync(A[i], w.ws_A, w.a_elems() * sizeof(float), hipMemcpyDeviceToDevice, s);

@@ -81,7 +81,7 @@ struct lenia_plan_ {
     // batched execution
     lenia::WorldArgs* d_tables[2] = {nullptr, nullptr};   // phase 0: X -> ws, 1: ws -> X
     int2* d_items = nullptr;
-    int n_items = 0, grid = 0;
+    int n_items = 0;
     std::vector<float*> graph_A, graph_P;                 // pointer set of the graph
     hipGraphExec_t graph = nullptr;
     hipStream_t capture_stream = nullptr;                 // private stream used for capture

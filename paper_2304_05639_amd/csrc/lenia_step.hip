@@ -398,27 +398,29 @@ epilogue_launch_fn find_epilogue_launcher(int table)
     return (table == TABLE_3x15) ? &launch_epilogue<Table3x15> : &launch_epilogue<Table1x1>;
 }
 
-// Batched form: the grid walks the (world, tile) work list.  It is launched
-// with one workgroup per item, so that the hardware dispatcher balances tiles
-// of uneven cost; a smaller grid strides over the list.
+// Batched form: one workgroup per (world, tile) item of the work list, so
+// that the hardware dispatcher balances tiles of uneven cost.
 template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
     __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
     __shared__ int tile_flag;
-    // XCD-aware walk: the work list (tiles of a world in row order) is cut into
-    // 8 contiguous chunks, one per XCD, so that neighbouring tiles, whose halos
-    // overlap, are processed by workgroups sharing an L2
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    const int per_xcd = (gridDim.x + 7 - xcd) >> 3;        // workgroups on this XCD
-    const int chunk = (bl.n_items + 7) >> 3;
-    const int begin = xcd * chunk;
-    const int end = min(bl.n_items, begin + chunk);
-    for (int i = begin + slot; i < end; i += per_xcd) {
-        const int2 it = bl.items[i];
-        process_tile<T, R, TY, TX>(bl.worlds[it.x], it.y, mode, sA, &tile_flag);
-        __syncthreads();   // LDS reuse by the next item
-    }
+    // blocks map to items through the same XCD-aware permutation as tiles of
+    // a single world (the list holds the tiles of a world in row order); the
+    // world table is read-only for the launch, so it is read through the
+    // constant address space, where its fields are scalar loads no store aliases
+    typedef const __attribute__((address_space(4))) int cint;
+    if ((int)blockIdx.x >= bl.n_items) return;
+    const cint* item = (const cint*)(bl.items + xcd_tile(blockIdx.x, bl.n_items));
+    const int world = item[0], tile = item[1];
+    constexpr int NW = sizeof(WorldArgs) / sizeof(int);
+    static_assert(NW * sizeof(int) == sizeof(WorldArgs), "WorldArgs is a whole number of words");
+    const cint* src = (const cint*)(bl.worlds + world);
+    int words[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) words[i] = src[i];
+    const WorldArgs wd = __builtin_bit_cast(WorldArgs, words);
+    process_tile<T, R, TY, TX>(wd, tile, mode, sA, &tile_flag);
 }
 
 template <class T, int R, int TY, int TX>
@@ -430,10 +432,11 @@ hipError_t launch_step(const WorldArgs& w, int mode, hipStream_t s)
 }
 
 template <class T, int R, int TY, int TX>
-hipError_t launch_batch(const BatchList& b, int mode, int grid, hipStream_t s)
+hipError_t launch_batch(const BatchList& b, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(grid), dim3(step_threads<TY, TX>()), 0, s, b,
-                       mode);
+    if (b.n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((step_batch_kernel<T, R, TY, TX>), dim3(b.n_items), dim3(step_threads<TY, TX>()), 0, s,
+                       b, mode);
     return hipGetLastError();
 }
 

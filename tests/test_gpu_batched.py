@@ -47,6 +47,25 @@ def test_batched_equals_single(L, n_steps):
         assert torch.equal(a, A) and torch.equal(p, P), (w.name, n_steps)
 
 
+def test_batched_many_tiles_equals_single(L):
+    """More than 8 runs of 512 work items, so that blocks map to items through
+    the XCD run permutation and its tail: still every world bit for bit."""
+    import torch
+    sizes = [(512, 512), (512, 512), (512, 512), (512, 512), (200, 264), (96, 64)]
+    worlds = [inputs.test_world(h, w, seed=320 + i, n_blobs=max(1, h * w // 2000))
+              for i, (h, w) in enumerate(sizes)]
+    bp = L.BatchedPlan(worlds, tile=(8, 32))
+    assert bp.info().tile_y == 8 and bp.info().tile_x == 32
+    As = [dev(w.A) for w in worlds]
+    Ps = [dev(w.P) for w in worlds]
+    bp.step(As, Ps, n_steps=2)
+    torch.cuda.synchronize()
+    for w, A, P in zip(worlds, As, Ps):
+        a, p = L.Plan(w, tile=(8, 32)).step(dev(w.A), dev(w.P), n_steps=2)
+        torch.cuda.synchronize()
+        assert torch.equal(a, A) and torch.equal(p, P), w.name
+
+
 def test_batched_graph_replay_and_pointer_change(L):
     """Repeated calls replay the captured graph; new buffers re-capture it."""
     import torch
