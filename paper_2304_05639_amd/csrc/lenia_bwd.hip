@@ -236,12 +236,16 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
 #pragma unroll
     for (int j = 0; j < KPS; ++j) src[j] = b.ubar + (size_t)T::kidx[s][j] * HW;
     src[KPS] = b.A + (size_t)s * HW;
-    // ubar is staged masked by alpha (only alpha cells hold it); A unmasked
+    // ubar is staged masked by alpha (only alpha cells hold it); A unmasked.
+    // Where no cell of the window has alpha, every staged ubar is 0, so the
+    // transposed convolution and the shell-height sums of the tile are exactly
+    // 0 and the orbit walk is skipped (the tile's outputs are still written).
+    bool kept = true;
     if (b.mode == MODE_LOCAL_UPDATE)
-        stage_planes<NPL, R, TY, TX, NT, PITCH, CHS, KPS>(sm, src, H, W, y0, x0, b.alpha);
+        kept = stage_planes<NPL, R, TY, TX, NT, PITCH, CHS, KPS>(sm, src, H, W, y0, x0, b.alpha);
     else
         stage_planes<NPL, R, TY, TX, NT, PITCH, CHS>(sm, src, H, W, y0, x0);
-    __syncthreads();
+    const bool active = __syncthreads_or(kept) != 0;
     float uc[KPS][Q];
 #pragma unroll
     for (int j = 0; j < KPS; ++j)
@@ -259,33 +263,35 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
     }
     cfloat* w = (cfloat*)b.wt + s * 8;
     cfloat* bc = (cfloat*)b.bt + s * 16;
+    if (active) {
 #pragma unroll 1
-    for (int a = 1; a < R; ++a, w += WS, bc += BS) {
-        float sum[NPL][Q];
-        quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-        orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
-    }
-#pragma unroll 1
-    for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
-        float sum[NPL][Q];
-        quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
-                                        c - a * PITCH + a, c - a * PITCH - a);
-        orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
-    }
-#pragma unroll 1
-    for (int a = 2; a < R; ++a) {
-#pragma unroll 1
-        for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
-            float s0[NPL][Q], s1[NPL][Q], sum[NPL][Q];
-            quad_planes<NPL, Q, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
-                                            c - a * PITCH + bb, c - a * PITCH - bb);
-            quad_planes<NPL, Q, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
-                                            c - bb * PITCH + a, c - bb * PITCH - a);
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-                for (int q = 0; q < Q; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+        for (int a = 1; a < R; ++a, w += WS, bc += BS) {
+            float sum[NPL][Q];
+            quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
             orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+        }
+#pragma unroll 1
+        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
+            float sum[NPL][Q];
+            quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
+                                            c - a * PITCH + a, c - a * PITCH - a);
+            orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+        }
+#pragma unroll 1
+        for (int a = 2; a < R; ++a) {
+#pragma unroll 1
+            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
+                float s0[NPL][Q], s1[NPL][Q], sum[NPL][Q];
+                quad_planes<NPL, Q, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
+                                                c - a * PITCH + bb, c - a * PITCH - bb);
+                quad_planes<NPL, Q, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
+                                                c - bb * PITCH + a, c - bb * PITCH - a);
+#pragma unroll
+                for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+                orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+            }
         }
     }
     // shell-height partials of this tile: ubar at the cell times its

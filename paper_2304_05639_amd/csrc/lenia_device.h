@@ -90,11 +90,13 @@ __device__ __forceinline__ void wrap2(int& gy, int& gx, int H, int W, bool singl
 // into dst[p * CHS + yy * PITCH + xx], using NT threads with all of a thread's
 // loads in flight before the LDS writes.
 // The first NM planes are masked: a position whose mask byte is 0 stages 0.
+// Returns whether any of the thread's positions had a nonzero mask byte.
 template <int NPL, int R, int TY, int TX, int NT, int PITCH, int CHS, int NM = 0>
-__device__ __forceinline__ void stage_planes(float* dst, const float* const (&src)[NPL], int H,
+__device__ __forceinline__ bool stage_planes(float* dst, const float* const (&src)[NPL], int H,
                                              int W, int y0, int x0,
                                              const uint8_t* mask = nullptr)
 {
+    bool any_kept = false;
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
     constexpr int NG = PY * PX;
     constexpr int IT = (NG + NT - 1) / NT;
@@ -113,6 +115,7 @@ __device__ __forceinline__ void stage_planes(float* dst, const float* const (&sr
             wrap2(gy, gx, H, W, single_wrap);
             const uint32_t o = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
             const bool keep = (NM == 0) || (mask[o] != 0);
+            any_kept = any_kept || keep;
 #pragma unroll
             for (int p = 0; p < NPL; ++p) v[it][p] = (p < NM && !keep) ? 0.f : pld(pl[p], 4u * o);
         }
@@ -127,6 +130,7 @@ __device__ __forceinline__ void stage_planes(float* dst, const float* const (&sr
             for (int p = 0; p < NPL; ++p) dst[p * CHS + yy * PITCH + xx] = v[it][p];
         }
     }
+    return any_kept;
 }
 
 }  // namespace lenia
