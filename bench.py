@@ -119,7 +119,7 @@ def batched_throughput(steps: int = 20, warmup: int = 2):
     from paper_2304_05639_amd import inputs, lenia
     worlds = inputs.config4()
     cells = sum(w.H * w.W for w in worlds)
-    bp = lenia.BatchedPlan(worlds)
+    bp = lenia.BatchedPlan(worlds, autotune=True)
     As = [torch.tensor(w.A, device="cuda") for w in worlds]
     Ps = [torch.tensor(w.P, device="cuda") for w in worlds]
     bp.step(As, Ps, n_steps=warmup)
