@@ -243,23 +243,30 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int txi = tile - tyi * wd.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
 
-    // An empty tile: the potentials u_k are averages (non-negative weights
-    // summing to 1) of their source channel over the window, so if some
-    // channel's window stays <= skip_thr < eps, every u_k reading it is below
-    // the cutoff and alpha = 0 on the whole tile (Section 2.2).  Then
-    // A' = clip01(A) and P' = 0 exactly, without the convolution.  Decided
-    // only where the potentials are not requested.
+    // Tiles where alpha = 0 everywhere (Section 2.2), found before the
+    // convolution, so that A' = clip01(A) and P' = 0 are written exactly
+    // without it.  Two sufficient conditions:
+    //  * an empty channel: the potentials u_k are averages (non-negative
+    //    weights summing to 1) of their source channel over the window, so if
+    //    some channel's window stays <= skip_thr < eps, every u_k reading it is
+    //    below the cutoff;
+    //  * a dead gene plane: if every value of gene plane 0 on the tile and its
+    //    1-cell ring is <= eps, no disk of the diffusion counts a value above
+    //    eps, so the diffused gene is 0 on the tile (P' = 0 where alpha was 0
+    //    leaves such regions behind).
+    // Decided only where the potentials are not requested.
     const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
     if (may_skip && threadIdx.x == 0) *tile_flag = 0;
-    int wave_bits = 0;   // bit c: some window value of channel c above skip_thr
+    int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr;
+                         // bit C: some value of gene plane 0 above eps
 
+    // a single wrap suffices unless the torus is smaller than tile + halo
+    const bool single_wrap = (H >= TY + R) && (W >= TX + R);
     // 1. stage A (+halo, wrapped) with all of a thread's loads in flight at once;
     // the index arithmetic of a halo position is shared by the channels
     {
         constexpr int NG = PY * PX;
         constexpr int IT = (NG + NT - 1) / NT;
-        // a single wrap suffices unless the torus is smaller than tile + halo
-        const bool single_wrap = (H >= TY + R) && (W >= TX + R);
         float v[IT][T::C];
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -301,14 +308,29 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
                     above = above || ((threadIdx.x + it * NT < NG) && (v[it][ch] > wd.skip_thr));
                 wave_bits |= (__ballot(above) != 0ull) ? (1 << ch) : 0;
             }
+            // gene plane 0 on the tile plus a 1-cell ring
+            constexpr int G1X = TX + 2, NG1 = (TY + 2) * G1X;
+            const plane_t p0 = plane(wd.P, 4u * (uint32_t)HW);
+            bool live = false;
+#pragma unroll
+            for (int i0 = 0; i0 < NG1; i0 += NT) {
+                const int i = i0 + (int)threadIdx.x;
+                if (i < NG1) {
+                    const int yy = i / G1X;
+                    int gy = y0 + yy - 1, gx = x0 + (i - yy * G1X) - 1;
+                    wrap2(gy, gx, H, W, single_wrap);
+                    live = live || (pld(p0, 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx)) > wd.eps);
+                }
+            }
+            wave_bits |= (__ballot(live) != 0ull) ? (1 << T::C) : 0;
         }
     }
     __syncthreads();
     if (may_skip) {
         if ((threadIdx.x & 63) == 0 && wave_bits != 0) atomicOr(tile_flag, wave_bits);
         __syncthreads();
-        if (*tile_flag != (1 << T::C) - 1) {
-            // some channel is empty on the window: alpha = 0 on the tile
+        if (*tile_flag != (2 << T::C) - 1) {
+            // an empty channel or a dead gene plane: alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
 #pragma unroll

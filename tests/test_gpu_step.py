@@ -106,14 +106,19 @@ def test_tiles_agree_bitwise(L):
         assert np.array_equal(A1, outs[0][0]) and np.array_equal(P1, outs[0][1])
 
 
-@pytest.mark.parametrize("tile", [(8, 32), (16, 32)])
-def test_empty_tile_shortcut_bitwise(L, tile):
-    """Tiles where some channel is empty over the whole window (tile + halo)
-    have alpha = 0 everywhere, so the step skips their convolution.  Asking
-    for the saved potentials turns the shortcut off; both must give identical
-    bits, on a world with empty and occupied tiles."""
+@pytest.mark.parametrize("tile,dead_genes", [((8, 32), False), ((16, 32), False), ((8, 32), True)])
+def test_empty_tile_shortcut_bitwise(L, tile, dead_genes):
+    """Tiles where some channel is empty over the whole window (tile + halo),
+    or where gene plane 0 is at or below eps on the tile and its ring, have
+    alpha = 0 everywhere, so the step skips their convolution.  Asking for the
+    saved potentials turns the shortcut off; both must give identical bits, on
+    a world with empty and occupied tiles (and, with dead_genes, a band of
+    matter whose genes were masked to 0 by an earlier step)."""
     w = inputs.test_world(256, 320, seed=116, n_blobs=4)
     assert (w.A == 0).all(axis=0).mean() > 0.5          # mostly empty space
+    if dead_genes:
+        w.A[:, 100:180, :] = np.maximum(w.A[:, 100:180, :], 0.3)
+        w.P[:, :, 96:184, 40:300] = 0.0
     plan = L.Plan(w, tile=tile)
     a1, p1 = gpu_step(plan, w.A, w.P)
     a2, p2 = gpu_step(plan, w.A, w.P, saved=plan.new_saved())
