@@ -213,6 +213,44 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
     }
 }
 
+// Outputs of the thread's Q vertically adjacent cells (gy + q, gx) whose alpha
+// is 0 (no growth, genes masked to 0): A' = clip01(A), P' = 0.  c points at the
+// first cell in the staged tile of channel 0; cells past the torus edge are
+// skipped.  Planes are the outer loop, so each plane's descriptor is used for
+// all the cells and then dropped.
+template <class T, int Q, int PITCH, int CHS>
+__device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const float* c, int gy, int gx)
+{
+    const size_t HW = (size_t)wd.H * wd.W;
+    const uint32_t pb = 4u * (uint32_t)HW;
+    uint32_t ob[Q];
+    bool in[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        in[q] = (gy + q < wd.H) && (gx < wd.W);
+        ob[q] = 4u * ((uint32_t)(gy + q) * (uint32_t)wd.W + (uint32_t)gx);
+    }
+#pragma unroll
+    for (int ch = 0; ch < T::C; ++ch) {
+        const plane_t pl = plane(wd.A_out + (size_t)ch * HW, pb);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (in[q]) pst(pl, ob[q], clip01(c[ch * CHS + q * PITCH]));
+    }
+#pragma unroll
+    for (int p = 0; p < 3 * T::NK; ++p) {
+        const plane_t pl = plane(wd.P_out + (size_t)p * HW, pb);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (in[q]) pst(pl, ob[q], 0.f);
+    }
+    if (wd.alpha_save) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (in[q]) wd.alpha_save[ob[q] >> 2] = 0;
+    }
+}
+
 // Cells per thread: tiles of at most 256 cells give each thread one cell (for
 // small worlds, where parallelism is short), larger tiles a vertical pair.
 template <int TY, int TX>
@@ -333,21 +371,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             // an empty channel or a dead gene plane: alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
-#pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int gy = y0 + ly + q, gx = x0 + lx;
-                if (gy < H && gx < W) {
-                    const uint32_t ob = 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx);
-                    const uint32_t pb = 4u * (uint32_t)HW;
-                    const float* c = sA + (ly + q + R) * PITCH + (lx + R);
-#pragma unroll
-                    for (int ch = 0; ch < T::C; ++ch)
-                        pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(c[ch * CHS]));
-#pragma unroll
-                    for (int p = 0; p < 3 * NK; ++p) pst(plane(wd.P_out + (size_t)p * HW, pb), ob, 0.f);
-                    if (wd.alpha_save) wd.alpha_save[ob >> 2] = 0;
-                }
-            }
+            write_dead_cells<T, Q, PITCH, CHS>(wd, sA + (ly + R) * PITCH + (lx + R), y0 + ly, x0 + lx);
             return;
         }
     }
