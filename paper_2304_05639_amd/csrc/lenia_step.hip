@@ -1,9 +1,12 @@
 // Fused Lenia step for gfx950: direct torus convolution + gene diffusion +
 // alpha mask + growth + clipped update in one pass over a tile.
 //
-// Per output tile (TY x TX cells) a 256-thread workgroup
+// Per output tile (TY x TX cells) a workgroup (one thread per cell, or per
+// vertical pair of cells in tiles of more than 256 cells)
 //   1. stages the tile plus an R-cell halo of every channel of A into LDS
-//      (wrapped on the torus, so tiny tori accumulate multiply-wrapped taps);
+//      (wrapped on the torus, so tiny tori accumulate multiply-wrapped taps),
+//      and, where alpha is provably 0 on the whole tile (an empty channel or
+//      a dead gene plane), writes A' = clip01(A), P' = 0 and stops;
 //   2. per cell, forms the potentials u_k = K~_k * A_src(k) (Section 2.1) by
 //      summing each lattice-symmetry orbit of taps once per source channel and
 //      multiplying by the orbit weight of each kernel reading that channel;
@@ -24,19 +27,13 @@ namespace lenia {
 #define LENIA_MIN_WAVES 2   // minimum waves per SIMD the register budget must allow
 #endif
 
-
 // Kernel weights, per orbit t and source channel s: wt[(t * C + s) * 8 + j] is
 // the weight of the j-th kernel reading channel s (slot order of the table);
 // the index is uniform, so these are scalar loads.
 
-// Potentials of a vertical pair of cells (c and c + PITCH):
-//   u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
-// The offsets are walked orbit by orbit in three branch-free loops, in the
-// order of the weight table: axis orbits (a, 0), diagonal orbits (a, a), then
-// general orbits (a, b), 0 < b < a (all with a^2 + b^2 < R^2).  Each orbit's
-// cells are summed once per source channel and multiplied once per kernel.
-// `c` points at the upper cell in the LDS tile of channel 0; channel s is CHS
-// floats further.
+// acc[q][s][j] += w[s][j] * sum[q][s]: one orbit's contribution to the
+// potentials of the Q cells, the orbit sum of each source channel times the
+// weight of each kernel reading it.
 template <class T, int Q, int PITCH, int CHS>
 __device__ __forceinline__ void orbit_fma(float (&acc)[Q][T::C][T::KPS], const float (&sum)[Q][T::C],
                                           cfloat* w)
