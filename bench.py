@@ -144,12 +144,13 @@ MFMA_FLOPS = 16 * 16 * 32 * 2
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def dft_form(world, steps: int = 20, warmup: int = 2):
-    """The split-bf16 DFT-as-GEMM form on the same world: full-step throughput,
-    and the MFMA kernel alone (lenia_potentials) against the dense bf16 peak."""
+def dft_form(world, steps: int = 20, warmup: int = 2, conv: int = 2):
+    """A split DFT-as-GEMM form (bf16 or fp16 hi+lo operands) on the same world:
+    full-step throughput, and the MFMA kernel alone (lenia_potentials) against
+    the dense peak of its operand type (2.5 PFLOP/s for both)."""
     import torch
     from paper_2304_05639_amd import lenia
-    plan = lenia.Plan(world, conv=lenia.CONV_DFT_SPLIT_BF16)
+    plan = lenia.Plan(world, conv=conv)
     V = plan.info().tile_y
     n_tiles = -(-world.H // V) * -(-world.W // V)
     A = torch.tensor(world.A, device="cuda")
@@ -177,8 +178,8 @@ def dft_form(world, steps: int = 20, warmup: int = 2):
             "ms_per_step": s_ms, "mfma_kernel_ms": k_ms,
             "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
-                         "traffic": measured_traffic(world.H * world.W, DFT_TRAFFIC_FILE,
-                                                     DFT_SRCS)},
+                         "traffic": (measured_traffic(world.H * world.W, DFT_TRAFFIC_FILE, DFT_SRCS)
+                                     if conv == lenia.CONV_DFT_SPLIT_BF16 else None)},
             "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile"}
 
 
@@ -221,7 +222,8 @@ def main():
         return
     world = inputs.config3()
     if args.only == "dft":
-        print(json.dumps({"dft_split_bf16": dft_form(world)}), flush=True)
+        print(json.dumps({"dft_split_bf16": dft_form(world),
+                          "dft_split_f16": dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)}), flush=True)
         return
     cells = world.H * world.W
     tile = tuple(int(x) for x in args.tile.split("x")) if args.tile else None
@@ -278,6 +280,7 @@ def main():
     del A2, P2, A, P
     if not args.no_dft and args.conv == "direct":
         out["dft_split_bf16"] = dft_form(world)
+        out["dft_split_f16"] = dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)
     if args.calibrate:
         src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

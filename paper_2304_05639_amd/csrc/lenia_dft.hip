@@ -12,10 +12,12 @@
 //   GEMM3  [Z_re; Z_im]^T    (64 x 2V)  = [U_re; U_im]^T [[C_V, -S_V], [S_V, C_V]]^T
 //   GEMM4  u_k               (V x V)    = [Z_re | Z_im] [C'_V; -S'_V]
 // where C_V / S_V keep the V output rows (columns) of the inverse transform.
-// Every GEMM runs in bf16 on v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
-// each operand x is split as hi = bf16(x), lo = bf16(x - hi) and a product is
-// hi*hi + hi*lo + lo*hi (about 16 significant bits).  The DFT matrices are
-// built in FP64 on the host and split there; data operands are split here.
+// Every GEMM runs on v_mfma_f32_16x16x32_bf16 (or _f16) with FP32
+// accumulation; each operand x is split as hi = e(x), lo = e(x - hi) in the
+// operand type e and a product is hi*hi + hi*lo + lo*hi (about 16 significant
+// bits with bf16, about 22 with fp16 for operands of magnitude above 2^-3).
+// The DFT matrices are built in FP64 on the host and split there; data
+// operands are split here.
 //
 // MFMA operand layouts (16x16x32): lane l holds A[l % 16][8 (l / 16) + j] and
 // B[8 (l / 16) + j][l % 16] for j < 8; the 16 x 16 FP32 result has
@@ -33,9 +35,30 @@
 
 namespace lenia {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Operand types of the split products: bf16 (8 significant bits per part)
+// or fp16 (11 bits per part, a narrower exponent range).
+template <class E>
+struct Op;
+template <>
+struct Op<__bf16> {
+    typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+    typedef __bf16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ f32x4 mma(const v8& a, const v8& b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Op<_Float16> {
+    typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+    typedef _Float16 v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ f32x4 mma(const v8& a, const v8& b, f32x4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
 
 constexpr int DT = 64;                   // DFT tile
 constexpr int DT2 = 128;                 // real-embedded complex dimension
@@ -46,10 +69,10 @@ constexpr int ZC_P = DT2 + 8;
 constexpr int ZC_ROWS = 48;
 
 struct DftTables {
-    const __bf16* f1t;    // [2][128][64]  hi, lo of [C | -S]^T
-    const __bf16* f2;     // [2][128][128] hi, lo of [[C, S], [-S, C]]
-    const __bf16* f3;     // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
-    const __bf16* f4t;    // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
+    const void* f1t;      // [2][128][64]  hi, lo of [C | -S]^T
+    const void* f2;       // [2][128][128] hi, lo of [[C, S], [-S, C]]
+    const void* f3;       // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
+    const void* f4t;      // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
     const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2
 };
 
@@ -60,44 +83,53 @@ struct DftArgs {
     int H, W, tiles_x, n_tiles;
 };
 
-__device__ __forceinline__ f32x4 mma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
-                                      const bf16x8& bl, f32x4 c)
+template <class E>
+__device__ __forceinline__ f32x4 mma3(const typename Op<E>::v8& ah, const typename Op<E>::v8& al,
+                                      const typename Op<E>::v8& bh, const typename Op<E>::v8& bl, f32x4 c)
 {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+    c = Op<E>::mma(al, bh, c);
+    c = Op<E>::mma(ah, bl, c);
+    c = Op<E>::mma(ah, bh, c);
     return c;
 }
 
-__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo)
+template <class E>
+__device__ __forceinline__ void split8(const float (&x)[8], typename Op<E>::v8& hi, typename Op<E>::v8& lo)
 {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const __bf16 h = (__bf16)x[j];
+        const E h = (E)x[j];
         hi[j] = h;
-        lo[j] = (__bf16)(x[j] - (float)h);
+        lo[j] = (E)(x[j] - (float)h);
     }
 }
 
-__device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *(const bf16x8*)p; }
+template <class E>
+__device__ __forceinline__ typename Op<E>::v8 ld8(const E* p) { return *(const typename Op<E>::v8*)p; }
 
-// Writes 4 consecutive values (split) as bf16 hi / lo.
-__device__ __forceinline__ void st4_split(__bf16* hi, __bf16* lo, const f32x4& v)
+// Writes 4 consecutive values (split) as hi / lo.
+template <class E>
+__device__ __forceinline__ void st4_split(E* hi, E* lo, const f32x4& v)
 {
-    bf16x4 h, l;
+    typename Op<E>::v4 h, l;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const __bf16 b = (__bf16)v[j];
+        const E b = (E)v[j];
         h[j] = b;
-        l[j] = (__bf16)(v[j] - (float)b);
+        l[j] = (E)(v[j] - (float)b);
     }
-    *(bf16x4*)hi = h;
-    *(bf16x4*)lo = l;
+    *(typename Op<E>::v4*)hi = h;
+    *(typename Op<E>::v4*)lo = l;
 }
 
-template <class T, int R>
+template <class T, int R, class E>
 __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 {
+    typedef typename Op<E>::v8 ev8;
+    const E* f1t = (const E*)g.t.f1t;
+    const E* f2m = (const E*)g.t.f2;
+    const E* f3m = (const E*)g.t.f3;
+    const E* f4t = (const E*)g.t.f4t;
     constexpr int V = DT - 2 * R;
     constexpr int NK = T::NK;
     // LDS: the transformed channels (fp32) + a scratch region shared by the
@@ -106,13 +138,13 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     constexpr int SCRATCH_BF16 = 2 * DT * XS_P + 2 * DT * YT_P;
     static_assert(2 * ZC_ROWS * ZC_P <= SCRATCH_BF16, "scratch too small");
     __shared__ float xh[XH_FLOATS];
-    __shared__ __bf16 scr[SCRATCH_BF16];
-    __bf16* xs_hi = scr;
-    __bf16* xs_lo = scr + DT * XS_P;
-    __bf16* yt_hi = scr + 2 * DT * XS_P;
-    __bf16* yt_lo = yt_hi + DT * YT_P;
-    __bf16* zc_hi = scr;
-    __bf16* zc_lo = scr + ZC_ROWS * ZC_P;
+    __shared__ E scr[SCRATCH_BF16];
+    E* xs_hi = scr;
+    E* xs_lo = scr + DT * XS_P;
+    E* yt_hi = scr + 2 * DT * XS_P;
+    E* yt_lo = yt_hi + DT * YT_P;
+    E* zc_hi = scr;
+    E* zc_lo = scr + ZC_ROWS * ZC_P;
 
     const int H = g.H, W = g.W;
     const size_t HW = (size_t)H * W;
@@ -136,7 +168,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                 wrap2(gy, gx, H, W, single_wrap);
                 v[j] = g.A[(size_t)s * HW + (size_t)gy * W + gx];
             }
-            st4_split(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, v);
+            st4_split<E>(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, v);
         }
         __syncthreads();
         // GEMM1: wave w computes rows 16w..16w+15 of Y, all 8 column blocks
@@ -147,14 +179,14 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int k0 = 32 * ks + lk;
-                const bf16x8 ah = ld8(xs_hi + (16 * wave + lr) * XS_P + k0);
-                const bf16x8 al = ld8(xs_lo + (16 * wave + lr) * XS_P + k0);
+                const ev8 ah = ld8(xs_hi + (16 * wave + lr) * XS_P + k0);
+                const ev8 al = ld8(xs_lo + (16 * wave + lr) * XS_P + k0);
 #pragma unroll
                 for (int n = 0; n < 8; ++n) {
                     const int row = 16 * n + lr;
-                    const bf16x8 bh = ld8(g.t.f1t + row * DT + k0);
-                    const bf16x8 bl = ld8(g.t.f1t + DT2 * DT + row * DT + k0);
-                    acc[n] = mma3(ah, al, bh, bl, acc[n]);
+                    const ev8 bh = ld8(f1t + row * DT + k0);
+                    const ev8 bl = ld8(f1t + DT2 * DT + row * DT + k0);
+                    acc[n] = mma3<E>(ah, al, bh, bl, acc[n]);
                 }
             }
             // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 64][64 (c / 64) + i]
@@ -162,7 +194,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
             for (int n = 0; n < 8; ++n) {
                 const int c = 16 * n + lr;
                 const int off = (c % DT) * YT_P + DT * (c / DT) + 16 * wave + ld;
-                st4_split(yt_hi + off, yt_lo + off, acc[n]);
+                st4_split<E>(yt_hi + off, yt_lo + off, acc[n]);
             }
         }
         __syncthreads();
@@ -176,19 +208,19 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int k0 = 32 * ks + lk;
-                bf16x8 ah[2], al[2];
+                ev8 ah[2], al[2];
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
                     const int row = 16 * (2 * wave + m) + lr;
-                    ah[m] = ld8(g.t.f2 + row * DT2 + k0);
-                    al[m] = ld8(g.t.f2 + DT2 * DT2 + row * DT2 + k0);
+                    ah[m] = ld8(f2m + row * DT2 + k0);
+                    al[m] = ld8(f2m + DT2 * DT2 + row * DT2 + k0);
                 }
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
-                    const bf16x8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
-                    const bf16x8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
+                    const ev8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
+                    const ev8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
 #pragma unroll
-                    for (int m = 0; m < 2; ++m) acc[m][n] = mma3(ah[m], al[m], bh, bl, acc[m][n]);
+                    for (int m = 0; m < 2; ++m) acc[m][n] = mma3<E>(ah[m], al[m], bh, bl, acc[m][n]);
                 }
             }
             // Xh row r = 16 (2w + m) + ld + j, column f2 = 16n + lr  ->  xh[s][f2][r]
@@ -209,25 +241,25 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     constexpr int NB3 = (2 * V + 15) / 16;
     static_assert(NB3 == 5, "GEMM3 is laid out for 5 column blocks");
     const int nb3 = (wave == 0) ? 2 : 1;
-    bf16x8 b3h[2][4], b3l[2][4];
+    ev8 b3h[2][4], b3l[2][4];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int nt = (q == 0) ? wave : 4;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int row = 16 * nt + lr, k0 = 32 * ks + lk;
-            b3h[q][ks] = ld8(g.t.f3 + row * DT2 + k0);
-            b3l[q][ks] = ld8(g.t.f3 + 80 * DT2 + row * DT2 + k0);
+            b3h[q][ks] = ld8(f3m + row * DT2 + k0);
+            b3l[q][ks] = ld8(f3m + 80 * DT2 + row * DT2 + k0);
         }
     }
     // GEMM4: wave w < 3 handles output column block w; B fragments in registers
-    bf16x8 b4h[4], b4l[4];
+    ev8 b4h[4], b4l[4];
     {
         const int row = 16 * (wave < 3 ? wave : 0) + lr;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            b4h[ks] = ld8(g.t.f4t + row * DT2 + 32 * ks + lk);
-            b4l[ks] = ld8(g.t.f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
+            b4h[ks] = ld8(f4t + row * DT2 + 32 * ks + lk);
+            b4l[ks] = ld8(f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
         }
     }
 
@@ -257,10 +289,10 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                     u8[j] = x0v[j] * k0v[j];
                     u8[4 + j] = x1v[j] * k1v[j];
                 }
-                bf16x8 ah, al;
-                split8(u8, ah, al);
-                acc[0][m] = mma3(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
-                if (nb3 == 2) acc[1][m] = mma3(ah, al, b3h[1][ks], b3l[1][ks], acc[1][m]);
+                ev8 ah, al;
+                split8<E>(u8, ah, al);
+                acc[0][m] = mma3<E>(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
+                if (nb3 == 2) acc[1][m] = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc[1][m]);
             }
         }
         __syncthreads();    // previous kernel's GEMM4 finished reading Zc
@@ -275,7 +307,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int off = p * ZC_P + col0 + 16 * m + ld;
-                    st4_split(zc_hi + off, zc_lo + off, acc[q][m]);
+                    st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m]);
                 }
             }
         }
@@ -291,9 +323,9 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                 for (int m = 0; m < 3; ++m) {
                     const int row = 16 * m + lr;
-                    const bf16x8 ah = ld8(zc_hi + row * ZC_P + k0);
-                    const bf16x8 al = ld8(zc_lo + row * ZC_P + k0);
-                    o[m] = mma3(ah, al, b4h[ks], b4l[ks], o[m]);
+                    const ev8 ah = ld8(zc_hi + row * ZC_P + k0);
+                    const ev8 al = ld8(zc_lo + row * ZC_P + k0);
+                    o[m] = mma3<E>(ah, al, b4h[ks], b4l[ks], o[m]);
                 }
             }
             // u row p = 16m + ld + j, column q = 16w + lr
@@ -313,28 +345,35 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     }
 }
 
-template <class T, int R>
+template <class T, int R, class E>
 hipError_t launch_dft(const DftArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((dft_conv_kernel<T, R>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((dft_conv_kernel<T, R, E>), dim3(a.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 typedef hipError_t (*dft_launch_fn)(const DftArgs&, hipStream_t);
 
-static dft_launch_fn find_dft(int table, int R)
+template <class E>
+static dft_launch_fn find_dft_e(int table, int R)
 {
-    if (table == TABLE_3x15 && R == 12) return &launch_dft<Table3x15, 12>;
-    if (table == TABLE_3x15 && R == 13) return &launch_dft<Table3x15, 13>;
-    if (table == TABLE_1x1 && R == 12) return &launch_dft<Table1x1, 12>;
-    if (table == TABLE_1x1 && R == 13) return &launch_dft<Table1x1, 13>;
+    if (table == TABLE_3x15 && R == 12) return &launch_dft<Table3x15, 12, E>;
+    if (table == TABLE_3x15 && R == 13) return &launch_dft<Table3x15, 13, E>;
+    if (table == TABLE_1x1 && R == 12) return &launch_dft<Table1x1, 12, E>;
+    if (table == TABLE_1x1 && R == 13) return &launch_dft<Table1x1, 13, E>;
     return nullptr;
 }
 
-bool conv_form_supported(int conv, int table, int R)
+static dft_launch_fn find_dft(int conv, int table, int R)
 {
-    return conv == LENIA_CONV_DFT_SPLIT_BF16 && find_dft(table, R) != nullptr;
+    if (conv == LENIA_CONV_DFT_SPLIT_BF16) return find_dft_e<__bf16>(table, R);
+    if (conv == LENIA_CONV_DFT_SPLIT_F16) return find_dft_e<_Float16>(table, R);
+    return nullptr;
 }
+
+bool conv_is_dft(int conv) { return conv == LENIA_CONV_DFT_SPLIT_BF16 || conv == LENIA_CONV_DFT_SPLIT_F16; }
+
+bool conv_form_supported(int conv, int table, int R) { return find_dft(conv, table, R) != nullptr; }
 
 int dft_valid_side(int R) { return DT - 2 * R; }
 
@@ -391,12 +430,21 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
             const int f2i = k % DT;
             f4t[q * DT2 + k] = (k < DT) ? C(f2i, R + q) : -S(f2i, R + q);
         }
+    // hi = round(x), lo = round(x - hi) in the operand type of the plan's form
+    const bool f16 = (p->conv == LENIA_CONV_DFT_SPLIT_F16);
     auto split = [&](const std::vector<double>& m) {
         uint16_t* out = new uint16_t[2 * m.size()];
         for (size_t i = 0; i < m.size(); ++i) {
-            const uint16_t h = bf16_bits((float)m[i]);
-            out[i] = h;
-            out[m.size() + i] = bf16_bits((float)(m[i] - (double)bf16_value(h)));
+            if (f16) {
+                const _Float16 h = (_Float16)(float)m[i];
+                const _Float16 l = (_Float16)(float)(m[i] - (double)(float)h);
+                std::memcpy(&out[i], &h, 2);
+                std::memcpy(&out[m.size() + i], &l, 2);
+            } else {
+                const uint16_t h = bf16_bits((float)m[i]);
+                out[i] = h;
+                out[m.size() + i] = bf16_bits((float)(m[i] - (double)bf16_value(h)));
+            }
         }
         keep.push_back(out);
         return out;
@@ -430,9 +478,8 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
     }
     const struct {
         const std::vector<double>* m;
-        __bf16** dst;
-    } mats[4] = {{&f1t, (__bf16**)&w.dft_f1t}, {&f2, (__bf16**)&w.dft_f2},
-                 {&f3, (__bf16**)&w.dft_f3}, {&f4t, (__bf16**)&w.dft_f4t}};
+        void** dst;
+    } mats[4] = {{&f1t, &w.dft_f1t}, {&f2, &w.dft_f2}, {&f3, &w.dft_f3}, {&f4t, &w.dft_f4t}};
     for (const auto& mm : mats) {
         uint16_t* host = split(*mm.m);
         const size_t bytes = 2 * mm.m->size() * sizeof(uint16_t);
@@ -441,7 +488,7 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
             return set_error(LENIA_ERR_OUT_OF_MEMORY, "DFT tables");
         p->allocations.push_back(d);
         p->ws_bytes += bytes;
-        *mm.dst = (__bf16*)d;
+        *mm.dst = d;
         hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "uploading DFT tables");
     }
@@ -467,17 +514,17 @@ hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const
     DftArgs a{};
     a.A = A;
     a.U = U;
-    a.t.f1t = (const __bf16*)w.dft_f1t;
-    a.t.f2 = (const __bf16*)w.dft_f2;
-    a.t.f3 = (const __bf16*)w.dft_f3;
-    a.t.f4t = (const __bf16*)w.dft_f4t;
+    a.t.f1t = w.dft_f1t;
+    a.t.f2 = w.dft_f2;
+    a.t.f3 = w.dft_f3;
+    a.t.f4t = w.dft_f4t;
     a.t.khat = w.dft_khat;
     a.H = w.H;
     a.W = w.W;
     const int V = DT - 2 * w.R;
     a.tiles_x = (w.W + V - 1) / V;
     a.n_tiles = a.tiles_x * ((w.H + V - 1) / V);
-    dft_launch_fn fn = find_dft(p->table, p->R);
+    dft_launch_fn fn = find_dft(p->conv, p->table, p->R);
     if (!fn) return hipErrorInvalidValue;
     return fn(a, s);
 }

@@ -446,7 +446,7 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     std::vector<void*> keep;
     lenia_status st = LENIA_OK;
     for (int i = 0; i < n && st == LENIA_OK; ++i) st = build_world(p, &ds[i], p->worlds[i], s, keep);
-    if (st == LENIA_OK && p->conv == LENIA_CONV_DFT_SPLIT_BF16)
+    if (st == LENIA_OK && conv_is_dft(p->conv))
         st = build_dft_tables(p, p->worlds[0], s, keep);
     if (st == LENIA_OK && batched) {
         for (int ph = 0; ph < 2 && st == LENIA_OK; ++ph) {
@@ -544,7 +544,7 @@ lenia_status lenia_plan_get_info(lenia_plan_t p, lenia_plan_info* info)
     info->conv = p->conv;
     info->tile_y = p->tile_y;
     info->tile_x = p->tile_x;
-    if (p->conv == LENIA_CONV_DFT_SPLIT_BF16)
+    if (conv_is_dft(p->conv))
         info->tile_y = info->tile_x = dft_valid_side(p->R);
     info->n_worlds = (int32_t)p->worlds.size();
     int64_t cells = 0;
@@ -623,7 +623,7 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
             a.A_out = nA;
             a.P_out = upd ? nP : nullptr;
             hipError_t e;
-            if (p->conv == LENIA_CONV_DFT_SPLIT_BF16) {
+            if (conv_is_dft(p->conv)) {
                 // potentials on the MFMA units into the saved buffer (or the
                 // plan's workspace), then the per-cell epilogue reads them
                 float* U = saved ? (float*)saved : w.dft_u;
@@ -665,7 +665,7 @@ lenia_status lenia_potentials(lenia_plan_t p, const float* A, float* U, void* st
         WorldPlan& w = p->worlds[0];
         hipStream_t s = (hipStream_t)stream;
         hipError_t e;
-        if (p->conv == LENIA_CONV_DFT_SPLIT_BF16) {
+        if (conv_is_dft(p->conv)) {
             e = launch_dft_potentials(p, w, A, U, s);
         } else {
             WorldArgs a = w.args_template();

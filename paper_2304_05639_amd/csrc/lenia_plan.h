@@ -22,6 +22,7 @@ double raw_kernel_sum(int R, int B, const double* beta);
 void orbit_list(int R, std::vector<int>& a, std::vector<int>& b);
 int orbit_size(int a, int b);
 bool conv_form_supported(int conv, int table, int R);
+bool conv_is_dft(int conv);   // one of the split DFT-as-GEMM forms
 int dft_valid_side(int R);
 struct WorldPlan;
 lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s, std::vector<void*>& keep);
@@ -42,7 +43,7 @@ struct WorldPlan {
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
     float* d_bt = nullptr;         // the same in the step kernel's orbit order
     int* d_nshells = nullptr;      // [NK]
-    void* dft_f1t = nullptr;       // DFT form: transform matrices (bf16 hi / lo),
+    void* dft_f1t = nullptr;       // DFT forms: transform matrices (hi / lo parts),
     void* dft_f2 = nullptr;        //   kernel spectra and the potentials workspace
     void* dft_f3 = nullptr;
     void* dft_f4t = nullptr;

@@ -79,6 +79,13 @@ def test_unsupported_descriptors(changes):
     assert len(L.last_error()) > 0
 
 
+def test_convolution_forms_validate():
+    w = inputs.test_world(32, 32, seed=2, n_blobs=1)
+    for conv in (L.CONV_AUTO, L.CONV_DIRECT_F32, L.CONV_DFT_SPLIT_BF16, L.CONV_DFT_SPLIT_F16):
+        assert _ok(w, conv=conv) == L.OK, (conv, L.last_error())
+    assert _ok(w, conv=4) == L.ERR_INVALID_ARG
+
+
 def test_unknown_tile_and_flags():
     w = inputs.test_world(32, 32, seed=2, n_blobs=1)
     assert _ok(w, tile=(24, 24)) == L.ERR_UNSUPPORTED

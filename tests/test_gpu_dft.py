@@ -1,5 +1,5 @@
-"""GPU parity of the MFMA DFT-as-GEMM form (split-bf16 operands, FP32
-accumulation) against the FP64 oracle.  The potentials carry the form's
+"""GPU parity of the MFMA DFT-as-GEMM forms (split bf16 or fp16 operands,
+FP32 accumulation) against the FP64 oracle.  The potentials carry the form's
 rounding (about 16 significant bits per product, four transform stages), so
 they are compared with TOL_U; the state after the growth mapping, which can
 amplify a potential error by up to dt * max|G'| (24 at s = 0.01, dt = 0.2), is
@@ -17,6 +17,16 @@ pytestmark = pytest.mark.gpu
 TOL_U = 2e-5
 TOL_STATE_DFT = 5e-4
 AMB_TAU = 2e-5        # alpha-ambiguity band for this form (above its potential error)
+# The fp16 split keeps about 22 bits only for operands of magnitude 2^-3 and
+# above; smaller operands (the lo parts, and the small spectral products of
+# high frequencies) sit on fp16's subnormal grid 2^-24.  A tile's inverse
+# transform sums 64 x 64 spectral products, so its potentials can be off by
+# up to 4096 * 2^-25 = 1.2e-4 (measured 6.4e-5 on a dense 512^2 world), and
+# the state by that times dt max|G'| = 24.3.
+TOL_U_F16 = 1.2e-4
+TOL_STATE_F16 = 3e-3
+AMB_TAU_F16 = 1.2e-4
+TOLS = {2: (TOL_U, TOL_STATE_DFT, AMB_TAU), 3: (TOL_U_F16, TOL_STATE_F16, AMB_TAU_F16)}
 
 
 @pytest.fixture(scope="module")
@@ -29,10 +39,13 @@ def L():
     return lenia
 
 
-def _run(L, w, n_steps=1):
+FORMS = [2, 3]       # CONV_DFT_SPLIT_BF16, CONV_DFT_SPLIT_F16
+
+
+def _run(L, w, n_steps=1, conv=2):
     import torch
-    plan = L.Plan(w, conv=L.CONV_DFT_SPLIT_BF16)
-    assert plan.info().conv == L.CONV_DFT_SPLIT_BF16
+    plan = L.Plan(w, conv=conv)
+    assert plan.info().conv == conv
     saved = plan.new_saved() if n_steps == 1 else None
     A1, P1 = plan.step(dev(w.A), dev(w.P) if w.P is not None else None, n_steps=n_steps,
                        saved=saved)
@@ -41,55 +54,60 @@ def _run(L, w, n_steps=1):
     return host(A1), (host(P1) if P1 is not None else None), u
 
 
+@pytest.mark.parametrize("conv", FORMS)
 @pytest.mark.parametrize("H,W,seed,R", [(64, 64, 401, 12), (100, 150, 402, 12), (16, 16, 403, 12),
                                         (81, 120, 404, 13), (512, 512, 405, 12)])
-def test_dft_potentials_and_state(L, oracle, H, W, seed, R):
+def test_dft_potentials_and_state(L, oracle, H, W, seed, R, conv):
     w = inputs.test_world(H, W, seed=seed, n_blobs=max(1, H * W // 600), R=R)
+    tol_u, tol_state, tau = TOLS[conv]
     d = oracle.Desc(w.H, w.W, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta, w.dt, 1, 1,
-                    tau=AMB_TAU)
-    A1, P1, u = _run(L, w)
+                    tau=tau)
+    A1, P1, u = _run(L, w, conv=conv)
     r = oracle.step(d, w.A, w.P)
     eu = float(np.abs(u - r["U"]).max())
     ok = (r["amb"] & 1) == 0
     eA = float(np.abs(A1 - r["A"])[:, ok].max())
     eP = float(np.abs(P1 - r["P"])[:, :, ok].max())
-    print(f"DFT {H}x{W} R={R}: u err {eu:.2e}  A' err {eA:.2e}  P' err {eP:.2e}  "
+    print(f"DFT conv={conv} {H}x{W} R={R}: u err {eu:.2e}  A' err {eA:.2e}  P' err {eP:.2e}  "
           f"ambiguous {int((~ok).sum())}")
-    assert eu <= TOL_U
-    assert eA <= TOL_STATE_DFT and eP <= TOL_STATE_DFT
+    assert eu <= tol_u
+    assert eA <= tol_state and eP <= tol_state
 
 
-def test_dft_global_single_channel(L, oracle):
+@pytest.mark.parametrize("conv", FORMS)
+def test_dft_global_single_channel(L, oracle, conv):
     w = inputs.config1()
     d = oracle.Desc.from_world(w)
-    A1, _, u = _run(L, w)
+    A1, _, u = _run(L, w, conv=conv)
     r = oracle.step(d, w.A)
     eu = float(np.abs(u - r["U"]).max())
     eA = float(np.abs(A1 - r["A"]).max())
-    print(f"DFT global 64x64 R=13: u err {eu:.2e}  A' err {eA:.2e}")
-    assert eu <= TOL_U and eA <= TOL_STATE_DFT
+    print(f"DFT conv={conv} global 64x64 R=13: u err {eu:.2e}  A' err {eA:.2e}")
+    assert eu <= TOLS[conv][0] and eA <= TOLS[conv][1]
 
 
-def test_dft_deterministic_and_multistep(L):
+@pytest.mark.parametrize("conv", FORMS)
+def test_dft_deterministic_and_multistep(L, conv):
     w = inputs.test_world(128, 96, seed=406, n_blobs=6)
-    a = _run(L, w, n_steps=3)
-    b = _run(L, w, n_steps=3)
+    a = _run(L, w, n_steps=3, conv=conv)
+    b = _run(L, w, n_steps=3, conv=conv)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_dft_close_to_direct_form(L):
-    """The two forms compute the same convolution: their states after one step
+@pytest.mark.parametrize("conv", FORMS)
+def test_dft_close_to_direct_form(L, conv):
+    """The forms compute the same convolution: the potentials after one step
     differ by the DFT form's rounding only."""
     import torch
     w = inputs.test_world(200, 256, seed=407, n_blobs=20)
     pd = L.Plan(w)
-    pf = L.Plan(w, conv=L.CONV_DFT_SPLIT_BF16)
+    pf = L.Plan(w, conv=conv)
     sd, sf = pd.new_saved(), pf.new_saved()
     pd.step(dev(w.A), dev(w.P), saved=sd)
     pf.step(dev(w.A), dev(w.P), saved=sf)
     torch.cuda.synchronize()
     ud, uf = host(pd.saved_views(sd)[0]), host(pf.saved_views(sf)[0])
-    assert np.abs(ud - uf).max() <= TOL_U
+    assert np.abs(ud - uf).max() <= TOLS[conv][0]
 
 
 def test_potentials_entry_point(L, oracle):
@@ -97,7 +115,8 @@ def test_potentials_entry_point(L, oracle):
     import torch
     w = inputs.test_world(96, 160, seed=408, n_blobs=10)
     r = oracle.step(oracle.Desc.from_world(w), w.A, w.P)
-    for conv, tol in ((L.CONV_DIRECT_F32, 2e-6), (L.CONV_DFT_SPLIT_BF16, TOL_U)):
+    for conv, tol in ((L.CONV_DIRECT_F32, 2e-6), (L.CONV_DFT_SPLIT_BF16, TOL_U),
+                      (L.CONV_DFT_SPLIT_F16, TOL_U_F16)):
         plan = L.Plan(w, conv=conv)
         U = plan.potentials(dev(w.A))
         torch.cuda.synchronize()
