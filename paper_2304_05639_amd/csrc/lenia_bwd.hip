@@ -77,32 +77,66 @@ __global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
 #pragma unroll
     for (int j = 0; j < KPD; ++j) kk[j] = T::kdst[c][j];
 
-    // genes of the channel's kernels: diffused (update) or as stored (read-only)
+    // Every read of the thread is issued before the arithmetic that needs it
+    // (one round trip rather than one per gene plane): the genes of the
+    // channel's kernels (their r = 1 disks when they are diffused), the
+    // potentials and the incoming gene cotangents.
+    const Nbr nb = neighbours(gy, gx, H, W);
+    float pv[3][KPD][5];
+    if (update) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < KPD; ++j) {
+                const float* pl = b.P + (size_t)(p * NK + kk[j]) * HW;
+                pv[p][j][0] = pl[nb.ou];
+                pv[p][j][1] = pl[nb.ol];
+                pv[p][j][2] = pl[nb.oc];
+                pv[p][j][3] = pl[nb.orr];
+                pv[p][j][4] = pl[nb.od];
+            }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < KPD; ++j) pv[p][j][2] = (b.P + (size_t)(p * NK + kk[j]) * HW)[idx];
+    }
+    float u[KPD];
+#pragma unroll
+    for (int j = 0; j < KPD; ++j) u[j] = (b.U + (size_t)kk[j] * HW)[idx];
+    float gp1[3][KPD];
+    if (b.gP1) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < KPD; ++j) gp1[p][j] = (b.gP1 + (size_t)(p * NK + kk[j]) * HW)[idx];
+    } else {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int j = 0; j < KPD; ++j) gp1[p][j] = 0.f;
+    }
+
+    // genes: diffused (update) or as stored (read-only)
     float pd[3][KPD], rn[3][KPD];
     bool clip_ok[3][KPD];
-    const Nbr nb = neighbours(gy, gx, H, W);
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int j = 0; j < KPD; ++j) {
-            const float* pl = b.P + (size_t)(p * NK + kk[j]) * HW;
             if (update) {
-                const Diffused df = diffuse5(pl, nb.ou, nb.ol, nb.oc, nb.orr, nb.od, eps);
+                const Diffused df = diffuse_vals(pv[p][j], eps);
                 pd[p][j] = df.v;
                 const float inv = (df.n > 0) ? __builtin_amdgcn_rcpf((float)df.n) : 0.f;
                 const float qq = df.num * inv;
                 clip_ok[p][j] = (df.n > 0) && (qq >= 0.f) && (qq <= 1.f);
                 rn[p][j] = inv;
             } else {
-                pd[p][j] = pl[idx];
+                pd[p][j] = pv[p][j][2];
                 clip_ok[p][j] = true;
                 rn[p][j] = 1.f;
             }
         }
-    float u[KPD];
-#pragma unroll
-    for (int j = 0; j < KPD; ++j) u[j] = (b.U + (size_t)kk[j] * HW)[idx];
-
     // forward growth and pre-clip update (same arithmetic and order as the step
     // kernel: ascending kernel index within the channel)
     float sum = 0.f;
@@ -126,7 +160,7 @@ __global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             const size_t q = (size_t)(p * NK + kk[j]) * HW;
-            const float pb = (b.gP1 ? b.gP1[q + idx] : 0.f) + dd[p];
+            const float pb = gp1[p][j] + dd[p];
             if (update)
                 b.numbar[q + idx] = clip_ok[p][j] ? pb * rn[p][j] : 0.f;
             else
@@ -145,25 +179,84 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// Values of one tap for NPL planes and the thread's Q cells: v[plane][cell].
-template <int NPL, int Q, int PITCH, int CHS>
-__device__ __forceinline__ void tap_load_planes(float (&v)[NPL][Q], const float* p)
-{
-#pragma unroll
-    for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) v[pl][q] = p[pl * CHS + q * PITCH];
-}
+// LDS layout of the gather's NPL staged planes over NPOS positions (row pitch
+// PX positions): planes in groups of four interleaved per position, one
+// 16-byte vector each, and the remaining one to three planes interleaved in a
+// last group of width RW (with six planes: one group of four and a pair), so a
+// tap of every plane is one 128-bit and one 64-bit LDS read.
+template <int NPL, int NPOS, int PX>
+struct GatherLayout {
+    static constexpr int N4 = NPL / 4;
+    static constexpr int REM = NPL - 4 * N4;
+    static constexpr int RW = (REM == 0) ? 0 : (REM == 1) ? 1 : (REM == 2) ? 2 : 4;
+    static constexpr int RB = 4 * N4 * NPOS;   // first float of the last group
+    static constexpr int floats = RB + RW * NPOS;
 
-template <int NPL, int Q, int PITCH, int CHS>
-__device__ __forceinline__ void quad_planes(float (&sum)[NPL][Q], const float* p0, const float* p1,
-                                            const float* p2, const float* p3)
+    __device__ static __forceinline__ void store(float* d, int pos, const float (&v)[NPL])
+    {
+#pragma unroll
+        for (int g = 0; g < N4; ++g)
+            *reinterpret_cast<float4*>(d + g * 4 * NPOS + 4 * pos) =
+                make_float4(v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]);
+        if constexpr (RW == 1) d[RB + pos] = v[4 * N4];
+        if constexpr (RW == 2)
+            *reinterpret_cast<float2*>(d + RB + 2 * pos) = make_float2(v[4 * N4], v[4 * N4 + 1]);
+        if constexpr (RW == 4)
+            *reinterpret_cast<float4*>(d + RB + 4 * pos) =
+                make_float4(v[4 * N4], REM > 1 ? v[4 * N4 + 1] : 0.f, REM > 2 ? v[4 * N4 + 2] : 0.f, 0.f);
+    }
+
+    // A position of the staged tile as pointers to its first float in the
+    // groups of four and in the last group; offsets move both, so that taps at
+    // constant offsets from a base are immediate offsets of LDS reads.
+    struct Pos {
+        const float* a;
+        const float* b;
+        __device__ __forceinline__ Pos operator+(int dpos) const { return {a + 4 * dpos, b + RW * dpos}; }
+        __device__ __forceinline__ Pos operator-(int dpos) const { return {a - 4 * dpos, b - RW * dpos}; }
+    };
+    __device__ static __forceinline__ Pos at(const float* d, int pos) { return {d + 4 * pos, d + RB + RW * pos}; }
+
+    // v[plane][q] = staged value of the plane at position p + q * PX
+    template <int Q>
+    __device__ static __forceinline__ void load(float (&v)[NPL][Q], Pos p)
+    {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int o = q * PX;
+#pragma unroll
+            for (int g = 0; g < N4; ++g) {
+                const float4 x = *reinterpret_cast<const float4*>(p.a + g * 4 * NPOS + 4 * o);
+                v[4 * g][q] = x.x;
+                v[4 * g + 1][q] = x.y;
+                v[4 * g + 2][q] = x.z;
+                v[4 * g + 3][q] = x.w;
+            }
+            if constexpr (RW == 1) v[4 * N4][q] = p.b[o];
+            if constexpr (RW == 2) {
+                const float2 x = *reinterpret_cast<const float2*>(p.b + 2 * o);
+                v[4 * N4][q] = x.x;
+                v[4 * N4 + 1][q] = x.y;
+            }
+            if constexpr (RW == 4) {
+                const float4 x = *reinterpret_cast<const float4*>(p.b + 4 * o);
+                v[4 * N4][q] = x.x;
+                if constexpr (REM > 1) v[4 * N4 + 1][q] = x.y;
+                if constexpr (REM > 2) v[4 * N4 + 2][q] = x.z;
+            }
+        }
+    }
+};
+
+// sum = (t0 + t1) + (t2 + t3) for each (plane, cell)
+template <class L, int NPL, int Q, class P>
+__device__ __forceinline__ void quad_planes(float (&sum)[NPL][Q], P p0, P p1, P p2, P p3)
 {
     float v0[NPL][Q], v1[NPL][Q], v2[NPL][Q], v3[NPL][Q];
-    tap_load_planes<NPL, Q, PITCH, CHS>(v0, p0);
-    tap_load_planes<NPL, Q, PITCH, CHS>(v1, p1);
-    tap_load_planes<NPL, Q, PITCH, CHS>(v2, p2);
-    tap_load_planes<NPL, Q, PITCH, CHS>(v3, p3);
+    L::template load<Q>(v0, p0);
+    L::template load<Q>(v1, p1);
+    L::template load<Q>(v2, p2);
+    L::template load<Q>(v3, p3);
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
@@ -199,23 +292,74 @@ constexpr int bwd_cells_per_thread() { return (TY * TX <= 256) ? 1 : 2; }
 template <int TY, int TX>
 constexpr int bwd_threads() { return TY * TX / bwd_cells_per_thread<TY, TX>(); }
 
+// Orbit counts of the walk (axis, diagonal, general with a below a_end), in
+// the order of the weight table.
+template <int R>
+constexpr int n_axis_orbits() { return R - 1; }
+
+template <int R>
+constexpr int n_diag_orbits()
+{
+    int n = 0;
+    for (int a = 1; 2 * a * a < R * R; ++a) ++n;
+    return n;
+}
+
+template <int R>
+constexpr int n_general_orbits_below(int a_end)
+{
+    int n = 0;
+    for (int a = 2; a < a_end; ++a)
+        for (int bb = 1; bb < a; ++bb)
+            if (a * a + bb * bb < R * R) ++n;
+    return n;
+}
+
+// Where the walk is split between two threads of a cell: the first takes the
+// axis and diagonal orbits and the general orbits with a below the returned
+// value, the second the rest.  Costs per orbit in the ratio of their
+// instruction counts (4 taps: 3, 8 taps: 4).
+template <int R>
+constexpr int gather_split_a()
+{
+    const int ad = 3 * (n_axis_orbits<R>() + n_diag_orbits<R>());
+    const int total = ad + 4 * n_general_orbits_below<R>(R);
+    int best = 2, best_cost = total;
+    for (int a = 2; a <= R; ++a) {
+        const int c0 = ad + 4 * n_general_orbits_below<R>(a);
+        const int m = (c0 > total - c0) ? c0 : total - c0;
+        if (m < best_cost) {
+            best_cost = m;
+            best = a;
+        }
+    }
+    return best;
+}
+
 // One workgroup per (tile, source channel s): the transposed convolution into
 // gA_s, the shell-height partials of the kernels reading s, and the diffusion
-// transpose of the gene planes q with q % C == s.
-template <class T, int R, int TY, int TX>
-__global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(BwdArgs b)
+// transpose of the gene planes q with q % C == s.  S threads share each cell
+// (or vertical pair of cells): with S = 2 (for worlds of few tiles, to double
+// the waves in flight) they walk disjoint parts of the orbits and the second
+// hands its sums to the first through LDS, which adds them in a fixed order.
+template <class T, int R, int TY, int TX, int S>
+__global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel(BwdArgs b)
 {
+    static_assert(S == 1 || S == 2, "one or two threads per cell");
     constexpr int Q = bwd_cells_per_thread<TY, TX>();
-    constexpr int NT = bwd_threads<TY, TX>();
-    constexpr int NWV = NT / 64;
+    constexpr int NTC = bwd_threads<TY, TX>();   // threads per part of the walk
+    constexpr int NT = S * NTC;
+    constexpr int NWV = NTC / 64;
     constexpr int KPS = T::KPS;
     constexpr int NPL = KPS + 1;
-    constexpr int PY = TY + 2 * R;
-    constexpr int PITCH = tile_pitch<R, TX>();
-    constexpr int CHS = PY * PITCH;
+    constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
+    using L = GatherLayout<NPL, PY * PX, PX>;
     constexpr int WS = T::C * 8;     // weights per orbit
     constexpr int BS = T::C * 16;    // shell-height coefficients per orbit
-    __shared__ float sm[NPL * CHS];
+    constexpr int NV = Q * (1 + KPS * 3);   // sums a thread hands over
+    constexpr int SPLIT = gather_split_a<R>();
+    static_assert(S == 1 || L::floats >= NTC * NV, "hand-over fits the staging buffer");
+    __shared__ __attribute__((aligned(16))) float sm[L::floats];
     __shared__ float red[NWV][KPS * 3];
 
     const int H = b.H, W = b.W;
@@ -224,13 +368,15 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tyi = tile / b.tiles_x, txi = tile - tyi * b.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
-    const int ly = Q * (threadIdx.x / TX), lx = threadIdx.x % TX;
+    const int tc = (S == 1) ? (int)threadIdx.x : (int)threadIdx.x % NTC;
+    const int part = (S == 1) ? 0 : (int)threadIdx.x / NTC;   // wave-uniform
+    const int ly = Q * (tc / TX), lx = tc % TX;
     const int gy = y0 + ly, gx = x0 + lx;
     bool valid[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) valid[q] = (gy + q < H) && (gx < W);
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const float* c = sm + (ly + R) * PITCH + (lx + R);
+    const int wave = tc / 64, lane = tc % 64;
+    const typename L::Pos c = L::at(sm, (ly + R) * PX + (lx + R));   // the thread's first cell
 
     const float* src[NPL];
 #pragma unroll
@@ -242,15 +388,19 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
     // 0 and the orbit walk is skipped (the tile's outputs are still written).
     bool kept = true;
     if (b.mode == MODE_LOCAL_UPDATE)
-        kept = stage_planes<NPL, R, TY, TX, NT, PITCH, CHS, KPS>(sm, src, H, W, y0, x0, b.alpha);
+        kept = stage_planes<L, NPL, R, TY, TX, NT, KPS>(sm, src, H, W, y0, x0, b.alpha);
     else
-        stage_planes<NPL, R, TY, TX, NT, PITCH, CHS>(sm, src, H, W, y0, x0);
+        stage_planes<L, NPL, R, TY, TX, NT>(sm, src, H, W, y0, x0);
     const bool active = __syncthreads_or(kept) != 0;
     float uc[KPS][Q];
+    {
+        float cv[NPL][Q];
+        L::template load<Q>(cv, c);
 #pragma unroll
-    for (int j = 0; j < KPS; ++j)
+        for (int j = 0; j < KPS; ++j)
 #pragma unroll
-        for (int q = 0; q < Q; ++q) uc[j][q] = valid[q] ? c[j * CHS + q * PITCH] : 0.f;
+            for (int q = 0; q < Q; ++q) uc[j][q] = valid[q] ? cv[j][q] : 0.f;
+    }
     float g[Q];
     float v[Q][KPS][3];
 #pragma unroll
@@ -263,49 +413,93 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
     }
     cfloat* w = (cfloat*)b.wt + s * 8;
     cfloat* bc = (cfloat*)b.bt + s * 16;
+    // this part's range of general orbits
+    const int ga0 = (S == 2 && part == 1) ? SPLIT : 2;
+    const int ga1 = (S == 2 && part == 0) ? SPLIT : R;
     if (active) {
+        if (part == 0) {
 #pragma unroll 1
-        for (int a = 1; a < R; ++a, w += WS, bc += BS) {
-            float sum[NPL][Q];
-            quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-            orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
-        }
-#pragma unroll 1
-        for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
-            float sum[NPL][Q];
-            quad_planes<NPL, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a,
-                                            c - a * PITCH + a, c - a * PITCH - a);
-            orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
-        }
-#pragma unroll 1
-        for (int a = 2; a < R; ++a) {
-#pragma unroll 1
-            for (int bb = 1; bb < a && a * a + bb * bb < R * R; ++bb, w += WS, bc += BS) {
-                float s0[NPL][Q], s1[NPL][Q], sum[NPL][Q];
-                quad_planes<NPL, Q, PITCH, CHS>(s0, c + a * PITCH + bb, c + a * PITCH - bb,
-                                                c - a * PITCH + bb, c - a * PITCH - bb);
-                quad_planes<NPL, Q, PITCH, CHS>(s1, c + bb * PITCH + a, c + bb * PITCH - a,
-                                                c - bb * PITCH + a, c - bb * PITCH - a);
-#pragma unroll
-                for (int pl = 0; pl < NPL; ++pl)
-#pragma unroll
-                    for (int q = 0; q < Q; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+            for (int a = 1; a < R; ++a, w += WS, bc += BS) {
+                float sum[NPL][Q];
+                quad_planes<L, NPL, Q>(sum, c + a * PX, c - a * PX, c + a, c - a);
                 orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+            }
+#pragma unroll 1
+            for (int a = 1; 2 * a * a < R * R; ++a, w += WS, bc += BS) {
+                float sum[NPL][Q];
+                quad_planes<L, NPL, Q>(sum, c + a * PX + a, c + a * PX - a, c - a * PX + a,
+                                       c - a * PX - a);
+                orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+            }
+        } else {
+            constexpr int skip = n_axis_orbits<R>() + n_diag_orbits<R>() + n_general_orbits_below<R>(SPLIT);
+            w += skip * WS;
+            bc += skip * BS;
+        }
+        // general orbits: the four base positions (rows c +- a, columns c +- a)
+        // are formed once per a; the b loop is unrolled so that every tap is an
+        // immediate offset from one of them
+#pragma unroll 1
+        for (int a = ga0; a < ga1; ++a) {
+            const typename L::Pos rp = c + a * PX, rm = c - a * PX, cp = c + a, cm = c - a;
+#pragma unroll
+            for (int bb = 1; bb < R - 1; ++bb) {
+                if (bb < a && a * a + bb * bb < R * R) {
+                    float s0[NPL][Q], s1[NPL][Q], sum[NPL][Q];
+                    quad_planes<L, NPL, Q>(s0, rp + bb, rp - bb, rm + bb, rm - bb);
+                    quad_planes<L, NPL, Q>(s1, cp + bb * PX, cm + bb * PX, cp - bb * PX,
+                                           cm - bb * PX);
+#pragma unroll
+                    for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                        for (int q = 0; q < Q; ++q) sum[pl][q] = s0[pl][q] + s1[pl][q];
+                    orbit_bwd<T, NPL, Q>(g, v, sum, w, bc);
+                    w += WS;
+                    bc += BS;
+                }
+            }
+        }
+    }
+    if constexpr (S == 2) {
+        // the second part's sums go through the (no longer needed) staging buffer
+        __syncthreads();
+        float* ho = sm + tc;   // element e of the thread at ho[e * NTC]
+        if (part == 1) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                ho[(q * (1 + KPS * 3)) * NTC] = g[q];
+#pragma unroll
+                for (int j = 0; j < KPS; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) ho[(q * (1 + KPS * 3) + 1 + j * 3 + i) * NTC] = v[q][j][i];
+            }
+        }
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                g[q] += ho[(q * (1 + KPS * 3)) * NTC];
+#pragma unroll
+                for (int j = 0; j < KPS; ++j)
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) v[q][j][i] += ho[(q * (1 + KPS * 3) + 1 + j * 3 + i) * NTC];
             }
         }
     }
     // shell-height partials of this tile: ubar at the cell times its
     // coefficient-weighted orbit sums, reduced over the block in a fixed order
+    if (part == 0) {
 #pragma unroll
-    for (int j = 0; j < KPS; ++j)
+        for (int j = 0; j < KPS; ++j)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            float pr = 0.f;
+            for (int i = 0; i < 3; ++i) {
+                float pr = 0.f;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) pr = fmaf(uc[j][q], v[q][j][i], pr);
-            pr = wave_sum(pr);
-            if (lane == 0) red[wave][j * 3 + i] = pr;
-        }
+                for (int q = 0; q < Q; ++q) pr = fmaf(uc[j][q], v[q][j][i], pr);
+                pr = wave_sum(pr);
+                if (lane == 0) red[wave][j * 3 + i] = pr;
+            }
+    }
     __syncthreads();
     for (int e = threadIdx.x; e < KPS * 3; e += NT) {
         float acc = 0.f;
@@ -316,16 +510,19 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
     }
 
     // direct term from the cell pass + convolution transpose into channel s
+    if (part == 0) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        if (!valid[q]) continue;
-        const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
-        float* ga = b.gA + (size_t)s * HW;
-        ga[o] = ga[o] + g[q];
+        for (int q = 0; q < Q; ++q) {
+            if (!valid[q]) continue;
+            const uint32_t o = (uint32_t)(gy + q) * (uint32_t)W + (uint32_t)gx;
+            float* ga = b.gA + (size_t)s * HW;
+            ga[o] = ga[o] + g[q];
+        }
     }
-    // transpose of the gene diffusion: gP(y) = sum over the disk of numbar(y + d);
-    // numbar vanishes wherever alpha does, so cells whose 5-neighbourhood has
-    // no alpha skip the reads
+    // transpose of the gene diffusion: gP(y) = sum over the disk of numbar(y + d)
+    // for the planes pq = s + C i, i = part, part + S, ...; numbar vanishes
+    // wherever alpha does, so cells whose 5-neighbourhood has no alpha skip the
+    // reads
     if (b.mode == MODE_LOCAL_UPDATE) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -334,7 +531,7 @@ __global__ __launch_bounds__((bwd_threads<TY, TX>())) void bwd_gather_kernel(Bwd
             const bool au = b.alpha[nb.ou], al = b.alpha[nb.ol], ac = b.alpha[nb.oc],
                        ar = b.alpha[nb.orr], ad = b.alpha[nb.od];
             const bool any = au | al | ac | ar | ad;
-            for (int pq = s; pq < 3 * T::NK; pq += T::C) {
+            for (int pq = s + T::C * part; pq < 3 * T::NK; pq += T::C * S) {
                 const float* nbp = b.numbar + (size_t)pq * HW;
                 float val = 0.f;
                 if (any) {
@@ -370,15 +567,15 @@ __global__ __launch_bounds__(256) void bwd_beta_reduce_kernel(const float* part,
     if (threadIdx.x == 0 && i < n_shells[k]) gbeta[k * 3 + i] += red[0];
 }
 
-template <class T, int R, int TY, int TX>
+template <class T, int R, int TY, int TX, int S>
 hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipStream_t s)
 {
     const unsigned cells = (unsigned)a.H * (unsigned)a.W;
     hipLaunchKernelGGL((bwd_cell_kernel<T>), dim3((cells + 255) / 256, T::C), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX>), dim3(a.n_tiles, T::C),
-                       dim3(bwd_threads<TY, TX>()), 0, s, a);
+    hipLaunchKernelGGL((bwd_gather_kernel<T, R, TY, TX, S>), dim3(a.n_tiles, T::C),
+                       dim3(S * bwd_threads<TY, TX>()), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bwd_beta_reduce_kernel, dim3(T::NK * 3), dim3(256), 0, s, a.part, a.n_tiles,
@@ -388,20 +585,20 @@ hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipS
 
 typedef hipError_t (*bwd_launch_fn)(const BwdArgs&, const int*, float*, hipStream_t);
 
-// Gather-pass tile: 16 x 32 cells, or 8 x 32 when that leaves too few tiles to
-// fill the device.
+// Gather-pass tile: 16 x 32 cells, or, when that leaves too few tiles to fill
+// the device, 8 x 32 cells with two threads per cell.
 static bwd_launch_fn find_bwd(int table, int R, bool small)
 {
     if (!small) {
-        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 16, 32>;
-        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 16, 32>;
-        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 16, 32>;
-        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 16, 32>;
+        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 16, 32, 1>;
+        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 16, 32, 1>;
+        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 16, 32, 1>;
+        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 16, 32, 1>;
     } else {
-        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 8, 32>;
-        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 8, 32>;
-        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 8, 32>;
-        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 8, 32>;
+        if (table == TABLE_3x15 && R == 12) return &launch_bwd<Table3x15, 12, 8, 32, 2>;
+        if (table == TABLE_3x15 && R == 13) return &launch_bwd<Table3x15, 13, 8, 32, 2>;
+        if (table == TABLE_1x1 && R == 12) return &launch_bwd<Table1x1, 12, 8, 32, 2>;
+        if (table == TABLE_1x1 && R == 13) return &launch_bwd<Table1x1, 13, 8, 32, 2>;
     }
     return nullptr;
 }

@@ -66,8 +66,8 @@ __device__ __forceinline__ float growth(float u, float m, float s, float h)
     return h * (2.f * growth_bell(u - m, s) - 1.f);
 }
 
-// LDS row pitch of a staged tile: tile width + halo, rounded up to a multiple
-// of 64 floats so that every plane / row offset is a ds_read2st64 offset.
+// LDS row pitch of a staged single-channel tile: tile width + halo, rounded up
+// to a multiple of 64 floats so that every row offset is a ds_read2st64 offset.
 template <int R, int TX>
 constexpr int tile_pitch() { return ((TX + 2 * R + 63) / 64) * 64; }
 
@@ -87,11 +87,12 @@ __device__ __forceinline__ void wrap2(int& gy, int& gx, int H, int W, bool singl
 
 // Stages NPL planes (plane p at src[p], row-major H x W) of the tile whose
 // top-left output cell is (y0, x0), plus an R-cell halo wrapped on the torus,
-// into dst[p * CHS + yy * PITCH + xx], using NT threads with all of a thread's
+// into LDS: the values of position (yy, xx) of the padded tile go to
+// L::store(dst, yy * (TX + 2R) + xx, v).  NT threads, with all of a thread's
 // loads in flight before the LDS writes.
 // The first NM planes are masked: a position whose mask byte is 0 stages 0.
 // Returns whether any of the thread's positions had a nonzero mask byte.
-template <int NPL, int R, int TY, int TX, int NT, int PITCH, int CHS, int NM = 0>
+template <class L, int NPL, int R, int TY, int TX, int NT, int NM = 0>
 __device__ __forceinline__ bool stage_planes(float* dst, const float* const (&src)[NPL], int H,
                                              int W, int y0, int x0,
                                              const uint8_t* mask = nullptr)
@@ -124,10 +125,7 @@ __device__ __forceinline__ bool stage_planes(float* dst, const float* const (&sr
     for (int it = 0; it < IT; ++it) {
         const int i = threadIdx.x + it * NT;
         if (i < NG) {
-            const int yy = i / PX;
-            const int xx = i - yy * PX;
-#pragma unroll
-            for (int p = 0; p < NPL; ++p) dst[p * CHS + yy * PITCH + xx] = v[it][p];
+            L::store(dst, i, v[it]);
         }
     }
     return any_kept;
@@ -146,15 +144,21 @@ struct Diffused {
     int n;
 };
 
+// The same from the 5 values v = (up, left, centre, right, down).
+__device__ __forceinline__ Diffused diffuse_vals(const float (&v)[5], float eps)
+{
+    Diffused r;
+    r.num = (((v[0] + v[1]) + v[2]) + v[3]) + v[4];
+    r.n = (v[0] > eps) + (v[1] > eps) + (v[2] > eps) + (v[3] > eps) + (v[4] > eps);
+    r.v = (r.n > 0) ? clip01(r.num * __builtin_amdgcn_rcpf((float)r.n)) : 0.f;
+    return r;
+}
+
 __device__ __forceinline__ Diffused diffuse5(const float* pl, uint32_t ou, uint32_t ol,
                                              uint32_t oc, uint32_t orr, uint32_t od, float eps)
 {
-    const float vu = pl[ou], vl = pl[ol], vc = pl[oc], vr = pl[orr], vd = pl[od];
-    Diffused r;
-    r.num = (((vu + vl) + vc) + vr) + vd;
-    r.n = (vu > eps) + (vl > eps) + (vc > eps) + (vr > eps) + (vd > eps);
-    r.v = (r.n > 0) ? clip01(r.num * __builtin_amdgcn_rcpf((float)r.n)) : 0.f;
-    return r;
+    const float v[5] = {pl[ou], pl[ol], pl[oc], pl[orr], pl[od]};
+    return diffuse_vals(v, eps);
 }
 
 // Diffusion of one plane with byte offsets of the 5 disk cells (as diffuse5,
@@ -167,17 +171,32 @@ struct NbrB {
     uint32_t c, u, d, l, r;
 };
 
+// The 5 disk values of one plane, in the order up, left, centre, right, down.
+__device__ __forceinline__ void load_disk(float (&v)[5], plane_t pl, const NbrB& o)
+{
+    v[0] = pld(pl, o.u);
+    v[1] = pld(pl, o.l);
+    v[2] = pld(pl, o.c);
+    v[3] = pld(pl, o.r);
+    v[4] = pld(pl, o.d);
+}
+
+__device__ __forceinline__ float diffuse_disk(const float (&v)[5], float cs, float ncs)
+{
+    const float num = (((v[0] + v[1]) + v[2]) + v[3]) + v[4];
+    const float n = clip01(fmaf(v[0], cs, ncs)) + clip01(fmaf(v[1], cs, ncs)) +
+                    clip01(fmaf(v[2], cs, ncs)) + clip01(fmaf(v[3], cs, ncs)) +
+                    clip01(fmaf(v[4], cs, ncs));
+    // evaluated unconditionally (n = 0 gives inf or NaN, which the select drops)
+    const float d = clip01(num * __builtin_amdgcn_rcpf(n));
+    return (n > 0.f) ? d : 0.f;
+}
+
 __device__ __forceinline__ float diffuse5b(plane_t pl, const NbrB& o, float cs, float ncs)
 {
-    const float vu = pld(pl, o.u), vl = pld(pl, o.l), vc = pld(pl, o.c), vr = pld(pl, o.r),
-                vd = pld(pl, o.d);
-    const float num = (((vu + vl) + vc) + vr) + vd;
-    const float n = clip01(fmaf(vu, cs, ncs)) + clip01(fmaf(vl, cs, ncs)) +
-                    clip01(fmaf(vc, cs, ncs)) + clip01(fmaf(vr, cs, ncs)) +
-                    clip01(fmaf(vd, cs, ncs));
-    // evaluated unconditionally (n = 0 gives inf or NaN, which the select drops)
-    const float v = clip01(num * __builtin_amdgcn_rcpf(n));
-    return (n > 0.f) ? v : 0.f;
+    float v[5];
+    load_disk(v, pl, o);
+    return diffuse_disk(v, cs, ncs);
 }
 
 __device__ __forceinline__ NbrB neighbour_bytes(int gy, int gx, int H, int W)

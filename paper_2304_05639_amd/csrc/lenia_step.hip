@@ -26,6 +26,25 @@ namespace lenia {
 #ifndef LENIA_MIN_WAVES
 #define LENIA_MIN_WAVES 2   // minimum waves per SIMD the register budget must allow
 #endif
+#ifndef LENIA_GENE_GROUP
+#define LENIA_GENE_GROUP 3  // gene planes per group of disk reads in the epilogue
+#endif
+
+// Layout of the staged tile (TY + 2R rows of TX + 2R positions) in LDS.  A
+// position (y, x) starts at float (y * PITCH + x) * ES; its channel s is CHS
+// floats further.  With three channels they are interleaved, one 16-byte
+// vector per position (4th lane zero), so that a tap of every channel is one
+// 128-bit LDS read at an immediate offset from the cell; a single channel is
+// stored as a plane with rows padded to a multiple of 64 floats.
+template <class T, int R, int TY, int TX>
+struct TileLayout {
+    static constexpr bool interleaved = (T::C == 3);
+    static constexpr int ES = interleaved ? 4 : 1;
+    static constexpr int PITCH = interleaved ? (TX + 2 * R) : tile_pitch<R, TX>();
+    static constexpr int RS = ES * PITCH;   // floats per row
+    static constexpr int CHS = interleaved ? 1 : (TY + 2 * R) * PITCH;
+    static constexpr int floats = (interleaved ? 4 : T::C) * (TY + 2 * R) * PITCH;
+};
 
 // Kernel weights, per orbit t and source channel s: wt[(t * C + s) * 8 + j] is
 // the weight of the j-th kernel reading channel s (slot order of the table);
@@ -34,7 +53,7 @@ namespace lenia {
 // acc[q][s][j] += w[s][j] * sum[q][s]: one orbit's contribution to the
 // potentials of the Q cells, the orbit sum of each source channel times the
 // weight of each kernel reading it.
-template <class T, int Q, int PITCH, int CHS>
+template <class T, int Q>
 __device__ __forceinline__ void orbit_fma(float (&acc)[Q][T::C][T::KPS], const float (&sum)[Q][T::C],
                                           cfloat* w)
 {
@@ -48,42 +67,48 @@ __device__ __forceinline__ void orbit_fma(float (&acc)[Q][T::C][T::KPS], const f
         }
 }
 
-// Values of one tap for the thread's Q cells (c, c + PITCH, ...) and every
-// channel: p points at the tap of the first cell in channel 0; channel s is
-// CHS floats further.  With CHS and PITCH multiples of 64 floats all values
-// come from one address register (ds_read2st64 pairs).
-template <class T, int Q, int PITCH, int CHS>
+// Values of one tap for the thread's Q cells (one row apart) and every
+// channel: p points at the tap of the first cell.
+template <class T, int Q, class L>
 __device__ __forceinline__ void tap_load(float (&v)[Q][T::C], const float* p)
 {
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+    for (int q = 0; q < Q; ++q) {
+        if constexpr (L::interleaved) {
+            const float4 x = *reinterpret_cast<const float4*>(p + q * L::RS);
+            v[q][0] = x.x;
+            v[q][1] = x.y;
+            v[q][2] = x.z;
+        } else {
 #pragma unroll
-        for (int s = 0; s < T::C; ++s) v[q][s] = p[s * CHS + q * PITCH];
+            for (int s = 0; s < T::C; ++s) v[q][s] = p[s * L::CHS + q * L::RS];
+        }
+    }
 }
 
 // sum = (t0 + t1) + (t2 + t3) for each (cell, channel)
-template <class T, int Q, int PITCH, int CHS>
+template <class T, int Q, class L>
 __device__ __forceinline__ void quad_sum(float (&sum)[Q][T::C], const float* p0, const float* p1,
                                          const float* p2, const float* p3)
 {
     float v0[Q][T::C], v1[Q][T::C], v2[Q][T::C], v3[Q][T::C];
-    tap_load<T, Q, PITCH, CHS>(v0, p0);
-    tap_load<T, Q, PITCH, CHS>(v1, p1);
-    tap_load<T, Q, PITCH, CHS>(v2, p2);
-    tap_load<T, Q, PITCH, CHS>(v3, p3);
+    tap_load<T, Q, L>(v0, p0);
+    tap_load<T, Q, L>(v1, p1);
+    tap_load<T, Q, L>(v2, p2);
+    tap_load<T, Q, L>(v3, p3);
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int s = 0; s < T::C; ++s) sum[q][s] = (v0[q][s] + v1[q][s]) + (v2[q][s] + v3[q][s]);
 }
 
-// Potentials of Q vertically adjacent cells (c, c + PITCH, ...):
+// Potentials of Q vertically adjacent cells (c, c + RS, ...):
 //   u_k = sum over offsets d of K~_k(d) A_src(k)(x + d).
 // The offsets are walked orbit by orbit in three branch-free loops, in the
 // order of the weight table: axis orbits (a, 0), diagonal orbits (a, a), then
 // general orbits (a, b), 0 < b < a (all with a^2 + b^2 < R^2).  Each orbit's
 // cells are summed once per source channel and multiplied once per kernel.
-template <class T, int Q, int R, int PITCH, int CHS>
+template <class T, int Q, int R, class L>
 __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ wt,
                                            float (&u)[Q][T::NK])
 {
@@ -95,44 +120,45 @@ __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ 
         for (int s = 0; s < T::C; ++s)
 #pragma unroll
             for (int j = 0; j < T::KPS; ++j) acc[q][s][j] = 0.f;
+    constexpr int RS = L::RS, ES = L::ES;
     cfloat* w = wt;
     // axis orbits: (+-a, 0), (0, +-a)
 #pragma unroll 1
     for (int a = 1; a < R; ++a, w += WS) {
         float sum[Q][T::C];
-        quad_sum<T, Q, PITCH, CHS>(sum, c + a * PITCH, c - a * PITCH, c + a, c - a);
-        orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
+        quad_sum<T, Q, L>(sum, c + a * RS, c - a * RS, c + a * ES, c - a * ES);
+        orbit_fma<T, Q>(acc, sum, w);
     }
     // diagonal orbits: (+-a, +-a)
 #pragma unroll 1
     for (int a = 1; 2 * a * a < R * R; ++a, w += WS) {
         float sum[Q][T::C];
-        quad_sum<T, Q, PITCH, CHS>(sum, c + a * PITCH + a, c + a * PITCH - a, c - a * PITCH + a,
-                                   c - a * PITCH - a);
-        orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
+        quad_sum<T, Q, L>(sum, c + a * (RS + ES), c + a * (RS - ES), c - a * (RS - ES),
+                                   c - a * (RS + ES));
+        orbit_fma<T, Q>(acc, sum, w);
     }
     // general orbits: (+-a, +-b), (+-b, +-a), 0 < b < a.  For each a the four
     // base pointers (rows c +- a, columns c +- a) are formed once; the b loop is
     // unrolled so that every tap is an immediate offset from one of them.
 #pragma unroll 1
     for (int a = 2; a < R; ++a) {
-        const float* rp = c + a * PITCH;
-        const float* rm = c - a * PITCH;
-        const float* cp = c + a;
-        const float* cm = c - a;
+        const float* rp = c + a * RS;
+        const float* rm = c - a * RS;
+        const float* cp = c + a * ES;
+        const float* cm = c - a * ES;
 #pragma unroll
         for (int b = 1; b < R - 1; ++b) {
             if (b < a && a * a + b * b < R * R) {
                 float s0[Q][T::C], s1[Q][T::C];
-                quad_sum<T, Q, PITCH, CHS>(s0, rp + b, rp - b, rm + b, rm - b);
-                quad_sum<T, Q, PITCH, CHS>(s1, cp + b * PITCH, cm + b * PITCH, cp - b * PITCH,
-                                           cm - b * PITCH);
+                quad_sum<T, Q, L>(s0, rp + b * ES, rp - b * ES, rm + b * ES, rm - b * ES);
+                quad_sum<T, Q, L>(s1, cp + b * RS, cm + b * RS, cp - b * RS,
+                                           cm - b * RS);
                 float sum[Q][T::C];
 #pragma unroll
                 for (int q = 0; q < Q; ++q)
 #pragma unroll
                     for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
-                orbit_fma<T, Q, PITCH, CHS>(acc, sum, w);
+                orbit_fma<T, Q>(acc, sum, w);
                 w += WS;
             }
         }
@@ -173,13 +199,32 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
         for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
         float pd[NP];
         if (alpha) {
-            // diffuse every gene plane (Section 2.3) and test it against the cutoff
+            // diffuse every gene plane (Section 2.3) and test it against the
+            // cutoff.  The disks are read in groups of G planes, the next
+            // group's reads issued before the current group is reduced, so a
+            // wave has one round trip in flight rather than one per plane (the
+            // scheduling barriers keep the compiler from serialising them again).
+            constexpr int G = (NP % LENIA_GENE_GROUP == 0) ? LENIA_GENE_GROUP : 3, NG = NP / G;
+            static_assert(NP % G == 0, "gene planes come in threes");
             const NbrB nb = neighbour_bytes(gy, gx, H, W);
             const float cs = wd.cnt_scale, ncs = wd.cnt_bias;
+            float v[2][G][5];
 #pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                pd[q] = diffuse5b(plane(wd.P + (size_t)q * HW, pb), nb, cs, ncs);
-                alpha = alpha && (pd[q] > eps);
+            for (int i = 0; i < G; ++i) load_disk(v[0][i], plane(wd.P + (size_t)i * HW, pb), nb);
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                if (g + 1 < NG) {
+#pragma unroll
+                    for (int i = 0; i < G; ++i)
+                        load_disk(v[(g + 1) & 1][i], plane(wd.P + (size_t)((g + 1) * G + i) * HW, pb), nb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < G; ++i) {
+                    pd[g * G + i] = diffuse_disk(v[g & 1][i], cs, ncs);
+                    alpha = alpha && (pd[g * G + i] > eps);
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         if (alpha) {
@@ -212,10 +257,10 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 
 // Outputs of the thread's Q vertically adjacent cells (gy + q, gx) whose alpha
 // is 0 (no growth, genes masked to 0): A' = clip01(A), P' = 0.  c points at the
-// first cell in the staged tile of channel 0; cells past the torus edge are
+// first cell in the staged tile (channel 0); cells past the torus edge are
 // skipped.  Planes are the outer loop, so each plane's descriptor is used for
 // all the cells and then dropped.
-template <class T, int Q, int PITCH, int CHS>
+template <class T, int Q, class L>
 __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const float* c, int gy, int gx)
 {
     const size_t HW = (size_t)wd.H * wd.W;
@@ -232,7 +277,7 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
         const plane_t pl = plane(wd.A_out + (size_t)ch * HW, pb);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
-            if (in[q]) pst(pl, ob[q], clip01(c[ch * CHS + q * PITCH]));
+            if (in[q]) pst(pl, ob[q], clip01(c[ch * L::CHS + q * L::RS]));
     }
 #pragma unroll
     for (int p = 0; p < 3 * T::NK; ++p) {
@@ -258,16 +303,15 @@ constexpr int step_threads() { return TY * TX / step_cells_per_thread<TY, TX>();
 
 
 template <class T, int R, int TY, int TX>
-constexpr int tile_lds_floats() { return T::C * (TY + 2 * R) * tile_pitch<R, TX>(); }
+constexpr int tile_lds_floats() { return TileLayout<T, R, TY, TX>::floats; }
 
 // One tile of one world.  Each thread owns Q vertically adjacent cells.
 template <class T, int R, int TY, int TX>
 __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA,
                                              int* tile_flag)
 {
+    using L = TileLayout<T, R, TY, TX>;
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
-    constexpr int PITCH = tile_pitch<R, TX>();
-    constexpr int CHS = PY * PITCH;
     constexpr int NK = T::NK;
     constexpr int NT = step_threads<TY, TX>();
     constexpr int Q = step_cells_per_thread<TY, TX>();
@@ -330,8 +374,13 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             if (i < NG) {
                 const int yy = i / PX;
                 const int xx = i - yy * PX;
+                float* d = sA + (yy * L::PITCH + xx) * L::ES;
+                if constexpr (L::interleaved) {
+                    *reinterpret_cast<float4*>(d) = make_float4(v[it][0], v[it][1], v[it][2], 0.f);
+                } else {
 #pragma unroll
-                for (int ch = 0; ch < T::C; ++ch) sA[ch * CHS + yy * PITCH + xx] = v[it][ch];
+                    for (int ch = 0; ch < T::C; ++ch) d[ch * L::CHS] = v[it][ch];
+                }
             }
         }
         if (may_skip) {
@@ -368,7 +417,8 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             // an empty channel or a dead gene plane: alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
-            write_dead_cells<T, Q, PITCH, CHS>(wd, sA + (ly + R) * PITCH + (lx + R), y0 + ly, x0 + lx);
+            write_dead_cells<T, Q, L>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
+                                      x0 + lx);
             return;
         }
     }
@@ -378,9 +428,9 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int lx = threadIdx.x % TX;
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy >= H || gx >= W) return;
-    const float* c = sA + (ly + R) * PITCH + (lx + R);
+    const float* c = sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES;
     float u[Q][NK];
-    conv_cells<T, Q, R, PITCH, CHS>(c, (cfloat*)wd.wt, u);
+    conv_cells<T, Q, R, L>(c, (cfloat*)wd.wt, u);
     if (mode == MODE_POTENTIALS) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -396,7 +446,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
         if (gy + q < H) {
             float a[T::C];
 #pragma unroll
-            for (int ch = 0; ch < T::C; ++ch) a[ch] = c[ch * CHS + q * PITCH];
+            for (int ch = 0; ch < T::C; ++ch) a[ch] = c[ch * L::CHS + q * L::RS];
             epilogue_cell<T>(wd, mode, u[q], a, gy + q, gx);
         }
     }
@@ -405,7 +455,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
 template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_kernel(WorldArgs wd, int mode)
 {
-    __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
+    __shared__ __attribute__((aligned(16))) float sA[tile_lds_floats<T, R, TY, TX>()];
     __shared__ int tile_flag;
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA, &tile_flag);
 }
@@ -446,7 +496,7 @@ epilogue_launch_fn find_epilogue_launcher(int table)
 template <class T, int R, int TY, int TX>
 __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void step_batch_kernel(BatchList bl, int mode)
 {
-    __shared__ float sA[tile_lds_floats<T, R, TY, TX>()];
+    __shared__ __attribute__((aligned(16))) float sA[tile_lds_floats<T, R, TY, TX>()];
     __shared__ int tile_flag;
     // blocks map to items through the same XCD-aware permutation as tiles of
     // a single world (the list holds the tiles of a world in row order); the

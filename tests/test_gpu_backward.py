@@ -139,6 +139,70 @@ def test_vjp_dft_form(L, oracle, H, W, seed, conv):
     assert eA <= tol and eP <= tol and eb <= tol
 
 
+@pytest.mark.parametrize("seed", [231, 232])
+def test_vjp_large_world_patch(L, oracle, seed):
+    """A 1024^2 world, large enough for the gather's wide tiles (one thread per
+    vertical cell pair), with cotangents on a 48 x 48 patch only.  The exact
+    gradients then depend only on the state within 2R + 2 of the patch: on a
+    torus cropped to the patch +- (2R + 2) the oracle's VJP equals the full
+    world's on the patch +- R (gA) and +- 1 (gP), and the shell-height
+    gradients are sums over the patch.  Outside the patch +- R the GPU's gA
+    and gP must be exactly 0."""
+    import dataclasses
+    from scipy.ndimage import uniform_filter
+    H = W = 1024
+    NP = 48
+    w = inputs.test_world(H, W, seed=seed, n_blobs=H * W // 600)
+    R = w.R
+    M = 2 * R + 2
+    # the patch on the most matter
+    dens = uniform_filter(w.A.sum(0).astype(np.float64), size=NP, mode="wrap")
+    cy, cx = np.unravel_index(int(np.argmax(dens)), dens.shape)
+    py, px = (cy - NP // 2) % H, (cx - NP // 2) % W
+    rng = np.random.default_rng(seed)
+    rows_p = (py + np.arange(NP)) % H
+    cols_p = (px + np.arange(NP)) % W
+    gA1 = np.zeros_like(w.A)
+    gP1 = np.zeros_like(w.P)
+    gA1[np.ix_(range(3), rows_p, cols_p)] = rng.standard_normal((3, NP, NP))
+    gP1[np.ix_(range(3), range(15), rows_p, cols_p)] = rng.standard_normal((3, 15, NP, NP))
+    gA, gP, gb = _gpu_vjp(L, w, gA1, gP1)
+
+    # oracle on the cropped torus
+    n = NP + 2 * M
+    rows = (py - M + np.arange(n)) % H
+    cols = (px - M + np.arange(n)) % W
+    wc = dataclasses.replace(w, H=n, W=n, A=np.ascontiguousarray(w.A[:, rows][:, :, cols]),
+                             P=np.ascontiguousarray(w.P[:, :, rows][:, :, :, cols]))
+    d = oracle.Desc.from_world(wc)
+    g = oracle.step_vjp(d, wc.A, wc.P, np.ascontiguousarray(gA1[:, rows][:, :, cols]),
+                        np.ascontiguousarray(gP1[:, :, rows][:, :, :, cols]))
+    amb = g["amb"] != 0
+    inner = np.zeros((n, n), bool)
+    inner[M:M + NP, M:M + NP] = True
+    amb &= inner                       # ambiguity outside the patch does not reach it
+    boxA = np.zeros((n, n), bool)
+    boxA[M - R:M + NP + R, M - R:M + NP + R] = True
+    boxP = np.zeros((n, n), bool)
+    boxP[M - 1:M + NP + 1, M - 1:M + NP + 1] = True
+    okA = boxA & ~_dilate(amb, R)
+    okP = boxP & ~_dilate(amb, 1)
+    gA_c = gA[:, rows][:, :, cols]
+    gP_c = gP[:, :, rows][:, :, :, cols]
+    eA, eP = _rel(gA_c, g["gA"], okA), _rel(gP_c, g["gP"], okP)
+    print(f"1024^2 patch at ({py},{px}) seed {seed}: ambiguous {int(amb.sum())}, "
+          f"rel err gA {eA:.2e} gP {eP:.2e}")
+    assert okA.sum() > 0 and eA <= TOL_REL and eP <= TOL_REL
+    if not amb.any():
+        eb = _rel(gb, g["gbeta"])
+        print(f"  gbeta rel err {eb:.2e}")
+        assert eb <= 1e-4
+    # nothing outside the reach of the patch
+    far = np.ones((H, W), bool)
+    far[np.ix_((py - R + np.arange(NP + 2 * R)) % H, (px - R + np.arange(NP + 2 * R)) % W)] = False
+    assert (gA[:, far] == 0).all() and (gP[:, :, far] == 0).all()
+
+
 def test_vjp_gbeta_accumulates(L):
     import torch
     w = smooth_world(32, 32, 221)
