@@ -369,7 +369,9 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
     const int tyi = tile / b.tiles_x, txi = tile - tyi * b.tiles_x;
     const int y0 = tyi * TY, x0 = txi * TX;
     const int tc = (S == 1) ? (int)threadIdx.x : (int)threadIdx.x % NTC;
-    const int part = (S == 1) ? 0 : (int)threadIdx.x / NTC;   // wave-uniform
+    // wave-uniform; read from the first lane so that the compiler knows it, and
+    // the weight addresses that depend on it stay scalar
+    const int part = (S == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x / NTC);
     const int ly = Q * (tc / TX), lx = tc % TX;
     const int gy = y0 + ly, gx = x0 + lx;
     bool valid[Q];
@@ -520,10 +522,14 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
         }
     }
     // transpose of the gene diffusion: gP(y) = sum over the disk of numbar(y + d)
-    // for the planes pq = s + C i, i = part, part + S, ...; numbar vanishes
-    // wherever alpha does, so cells whose 5-neighbourhood has no alpha skip the
-    // reads
+    // for the planes pq = s + C i, i = part, part + S, ...  numbar holds values
+    // only where alpha does: the disk values are read unconditionally (always
+    // in bounds) and those of cells without alpha are dropped by a select, and
+    // cells whose 5-neighbourhood has no alpha skip the reads.  All of a cell's
+    // reads are issued before the sums.
     if (b.mode == MODE_LOCAL_UPDATE) {
+        constexpr int NPQ = 3 * T::NK / T::C;       // gene planes per source channel
+        constexpr int NPS = (NPQ + S - 1) / S;      // of them per part
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if (!valid[q]) continue;
@@ -531,17 +537,37 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
             const bool au = b.alpha[nb.ou], al = b.alpha[nb.ol], ac = b.alpha[nb.oc],
                        ar = b.alpha[nb.orr], ad = b.alpha[nb.od];
             const bool any = au | al | ac | ar | ad;
-            for (int pq = s + T::C * part; pq < 3 * T::NK; pq += T::C * S) {
-                const float* nbp = b.numbar + (size_t)pq * HW;
-                float val = 0.f;
-                if (any) {
-                    // numbar holds values only where alpha does
-                    const float vu = au ? nbp[nb.ou] : 0.f, vl = al ? nbp[nb.ol] : 0.f;
-                    const float vc = ac ? nbp[nb.oc] : 0.f, vr = ar ? nbp[nb.orr] : 0.f;
-                    const float vd = ad ? nbp[nb.od] : 0.f;
-                    val = (((vu + vl) + vc) + vr) + vd;
+            float val[NPS];
+#pragma unroll
+            for (int ii = 0; ii < NPS; ++ii) val[ii] = 0.f;
+            if (any) {
+                float dv[NPS][5];
+#pragma unroll
+                for (int ii = 0; ii < NPS; ++ii) {
+                    const int i = part + S * ii;
+                    if (i < NPQ) {
+                        const float* nbp = b.numbar + (size_t)(s + T::C * i) * HW;
+                        dv[ii][0] = nbp[nb.ou];
+                        dv[ii][1] = nbp[nb.ol];
+                        dv[ii][2] = nbp[nb.oc];
+                        dv[ii][3] = nbp[nb.orr];
+                        dv[ii][4] = nbp[nb.od];
+                    }
                 }
-                (b.gP + (size_t)pq * HW)[nb.oc] = val;
+#pragma unroll
+                for (int ii = 0; ii < NPS; ++ii) {
+                    if (part + S * ii < NPQ) {
+                        const float vu = au ? dv[ii][0] : 0.f, vl = al ? dv[ii][1] : 0.f;
+                        const float vc = ac ? dv[ii][2] : 0.f, vr = ar ? dv[ii][3] : 0.f;
+                        const float vd = ad ? dv[ii][4] : 0.f;
+                        val[ii] = (((vu + vl) + vc) + vr) + vd;
+                    }
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < NPS; ++ii) {
+                const int i = part + S * ii;
+                if (i < NPQ) (b.gP + (size_t)(s + T::C * i) * HW)[nb.oc] = val[ii];
             }
         }
     }
