@@ -27,6 +27,8 @@
  *   - U in the alpha mask is the normalized potential u_k = K~_k * A;
  *   - diffusion disk |d| <= r_diff inclusive; output 0 where the count is 0;
  *   - thresholds are strict (> eps); only the m, s, h genes are localized.
+ * The ring-decomposed kernels of Section 2.4, whose kernel genes are localized
+ * too, are a second step function, oracle_ring_step, at the end of the file.
  */
 #include <math.h>
 #include <stdint.h>
@@ -87,6 +89,33 @@ static inline long wrap(long i, long n)
     return r < 0 ? r + n : r;
 }
 
+/* Section 2.3: P_d = clip01((P * K_diff) / (Delta_same(P) * K_diff)) for NP
+ * planes, K_diff the disk |d| <= r_diff, 0 where no disk value exceeds eps.
+ * num, cnt receive the numerator and the count (may be NULL). */
+static void diffuse_planes(int H, int W, int NP, int rd, double eps, const double* P,
+                           double* num_out, double* cnt_out, double* Pd)
+{
+    const long N = (long)H * W;
+    #pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (int pk = 0; pk < NP; ++pk)
+            for (long x = 0; x < W; ++x) {
+                double num = 0.0, n = 0.0;
+                for (int dy = -rd; dy <= rd; ++dy)
+                    for (int dx = -rd; dx <= rd; ++dx) {
+                        if (dy * dy + dx * dx > rd * rd) continue;
+                        double v = P[(long)pk * N + wrap(y + dy, H) * W + wrap(x + dx, W)];
+                        num += v;
+                        if (v > eps) n += 1.0;
+                    }
+                long o = (long)pk * N + y * W + x;
+                if (num_out) num_out[o] = num;
+                if (cnt_out) cnt_out[o] = n;
+                double q = (n > 0.0) ? num / n : 0.0;
+                Pd[o] = (n > 0.0) ? fmax(fmin(q, 1.0), 0.0) : 0.0;
+            }
+}
+
 /* Forward internals of one step at every cell, shared by step and VJP. */
 typedef struct {
     int H, W, C, NK, R, localized, genotype_update, r_diff;
@@ -113,25 +142,7 @@ static void forward_internals(fwd_t* f)
     /* Section 2.3: diffusion of every gene plane (only when genes are updated). */
     if (f->localized) {
         if (f->genotype_update) {
-            int rd = f->r_diff;
-            #pragma omp parallel for schedule(static)
-            for (long y = 0; y < f->H; ++y)
-                for (int pk = 0; pk < NP; ++pk)
-                    for (long x = 0; x < f->W; ++x) {
-                        double num = 0.0, n = 0.0;
-                        for (int dy = -rd; dy <= rd; ++dy)
-                            for (int dx = -rd; dx <= rd; ++dx) {
-                                if (dy * dy + dx * dx > rd * rd) continue;
-                                double v = f->P[(long)pk * N + wrap(y + dy, f->H) * f->W + wrap(x + dx, f->W)];
-                                num += v;
-                                if (v > f->eps) n += 1.0;
-                            }
-                        long o = (long)pk * N + y * f->W + x;
-                        f->num[o] = num;
-                        f->cnt[o] = n;
-                        double q = (n > 0.0) ? num / n : 0.0;
-                        f->Pd[o] = (n > 0.0) ? fmax(fmin(q, 1.0), 0.0) : 0.0;
-                    }
+            diffuse_planes(f->H, f->W, NP, f->r_diff, f->eps, f->P, f->num, f->cnt, f->Pd);
         } else {
             memcpy(f->Pd, f->P, sizeof(double) * NP * N);
         }
@@ -452,5 +463,150 @@ ORACLE_EXPORT int oracle_beta_grad(int R, int B, const double* beta, const doubl
         gbeta[i] = (Z != 0.0) ? (dot - size * gk_dot_k) / Z : 0.0;
     }
     free(Kn);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Ring-decomposed localized kernels (Section 2.4).  Each kernel k carries, per
+ * cell, two bumps (r_i, w_i, b_i), i = 0, 1, of the kernel function
+ * kf(x; r, w, b) = b exp(-(x - r)^2 / (2 w^2)).  The disk |d| < R is split into
+ * n_ring rings; ring j holds the offsets with floor(n_ring |d| / R) = j and
+ * gets the weight kw_j = sum_i kf(j / n_ring; r_i, w_i, b_i) of the genes at
+ * the output cell.  The normalized potential is
+ *   u_k = sum_j kw_j (K_j * A_src(k)) / sum_j kw_j (K_j * 1),
+ * K_j the indicator of ring j, so K_j * 1 is the ring's number of offsets (a
+ * ring without lattice offsets adds nothing to either sum).  Gene tensor
+ * P[9][NK][H][W] in the paper's parameter order r1, w1, b1, r2, w2, b2, m, s,
+ * h.  Algorithm 2 otherwise as in the step above: every gene plane diffused,
+ * alpha = all u_k > eps and all diffused genes > eps, P' = alpha P_d, growth
+ * from the diffused m, s, h, A' = clip01(A + dt sum_k g_k) in ascending k.
+ * Readings: ring index by floor (the paper numbers rings r = 0 .. n_ring-1
+ * and evaluates the kernel function at r / n_ring); a bump with w <= 0
+ * contributes 0; u_k = 0 where the denominator is 0.
+ * ------------------------------------------------------------------------- */
+
+/* Ring of offset (dy, dx), -1 outside the open disk |d| < R. */
+ORACLE_EXPORT int oracle_ring_of(int R, int n_ring, int dy, int dx)
+{
+    long d2 = (long)dy * dy + (long)dx * dx;
+    if (d2 >= (long)R * R) return -1;
+    int j = (int)floor((double)n_ring * sqrt((double)d2) / (double)R);
+    return (j < n_ring) ? j : -1;
+}
+
+/* Number of offsets in each ring: n_r[j], j = 0 .. n_ring-1. */
+ORACLE_EXPORT void oracle_ring_sizes(int R, int n_ring, double* n_r)
+{
+    for (int j = 0; j < n_ring; ++j) n_r[j] = 0.0;
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+            int j = oracle_ring_of(R, n_ring, dy, dx);
+            if (j >= 0) n_r[j] += 1.0;
+        }
+}
+
+static double kernel_fn(double x, double r, double w, double b)
+{
+    if (!(w > 0.0)) return 0.0;
+    return b * exp(-(x - r) * (x - r) / (2.0 * w * w));
+}
+
+/*
+ * One step with ring kernels.  A[C][H][W], P[9][NK][H][W] (see above).
+ * Outputs A_out, P_out; optional U_out [NK][H][W], alpha_out, amb_out [H][W]
+ * (amb as for oracle_step).  Returns 0, or -1 on allocation failure.
+ */
+ORACLE_EXPORT int oracle_ring_step(int H, int W, int C, int NK, const int* src, const int* dst,
+                                   int R, int n_ring, double dt, double eps, int r_diff,
+                                   double tau, const double* A, const double* P,
+                                   double* A_out, double* P_out, double* U_out,
+                                   uint8_t* alpha_out, uint8_t* amb_out)
+{
+    const long N = (long)H * W;
+    const int NP = 9 * NK;
+    double* num = (double*)calloc((long)NP * N, sizeof(double));
+    double* cnt = (double*)calloc((long)NP * N, sizeof(double));
+    double* Pd = (double*)calloc((long)NP * N, sizeof(double));
+    double* ringsum = (double*)calloc((long)C * n_ring * N, sizeof(double));
+    double* U = (double*)calloc((long)NK * N, sizeof(double));
+    double* n_r = (double*)calloc(n_ring, sizeof(double));
+    if (!num || !cnt || !Pd || !ringsum || !U || !n_r) {
+        free(num); free(cnt); free(Pd); free(ringsum); free(U); free(n_r);
+        return -1;
+    }
+    /* Section 2.3: every gene plane is diffused */
+    diffuse_planes(H, W, NP, r_diff, eps, P, num, cnt, Pd);
+    oracle_ring_sizes(R, n_ring, n_r);
+
+    /* K_j * A_c: the sum of A_c over ring j around each cell (direct torus sum) */
+    #pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (int c = 0; c < C; ++c)
+            for (long x = 0; x < W; ++x) {
+                double* rs = ringsum + ((long)c * n_ring) * N + y * W + x;
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        int j = oracle_ring_of(R, n_ring, dy, dx);
+                        if (j < 0) continue;
+                        rs[(long)j * N] += A[(long)c * N + wrap(y + dy, H) * W + wrap(x + dx, W)];
+                    }
+            }
+
+    /* per-cell ring weights from the diffused genes, recombined potentials */
+    #pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c)
+        for (int k = 0; k < NK; ++k) {
+            double g[6];
+            for (int p = 0; p < 6; ++p) g[p] = Pd[(long)(p * NK + k) * N + c];
+            double nu = 0.0, de = 0.0;
+            for (int j = 0; j < n_ring; ++j) {
+                double x = (double)j / (double)n_ring;
+                double kw = kernel_fn(x, g[0], g[1], g[2]) + kernel_fn(x, g[3], g[4], g[5]);
+                nu += kw * ringsum[((long)src[k] * n_ring + j) * N + c];
+                de += kw * n_r[j];
+            }
+            U[(long)k * N + c] = (de > 0.0) ? nu / de : 0.0;
+        }
+
+    /* Section 2.2 alpha, Algorithm 2 mask, growth and clipped update */
+    #pragma omp parallel for schedule(static)
+    for (long c = 0; c < N; ++c) {
+        int a = 1;
+        uint8_t b = 0;
+        for (int k = 0; k < NK; ++k) {
+            double u = U[(long)k * N + c];
+            if (!(u > eps)) a = 0;
+            if (fabs(u - eps) <= tau) b |= 1;
+        }
+        for (int pk = 0; pk < NP; ++pk) {
+            double v = Pd[(long)pk * N + c];
+            if (!(v > eps)) a = 0;
+            if (fabs(v - eps) <= tau) b |= 1;
+            double n = cnt[(long)pk * N + c];
+            if (n > 0.0) {
+                double q = num[(long)pk * N + c] / n;
+                if (fabs(q) <= tau || fabs(q - 1.0) <= tau) b |= 2;
+            }
+        }
+        for (int ch = 0; ch < C; ++ch) {
+            double sum = 0.0;
+            for (int k = 0; k < NK; ++k) {
+                if (dst[k] != ch || !a) continue;
+                double m = Pd[(long)(6 * NK + k) * N + c];
+                double s = Pd[(long)(7 * NK + k) * N + c];
+                double h = Pd[(long)(8 * NK + k) * N + c];
+                double d = U[(long)k * N + c] - m;
+                sum += h * (2.0 * exp(-d * d / (2.0 * s * s)) - 1.0);
+            }
+            double z = A[(long)ch * N + c] + dt * sum;
+            if (fabs(z) <= tau || fabs(z - 1.0) <= tau) b |= 2;
+            A_out[(long)ch * N + c] = fmax(fmin(z, 1.0), 0.0);
+        }
+        for (int pk = 0; pk < NP; ++pk) P_out[(long)pk * N + c] = a ? Pd[(long)pk * N + c] : 0.0;
+        if (alpha_out) alpha_out[c] = (uint8_t)a;
+        if (amb_out) amb_out[c] = b;
+    }
+    if (U_out) memcpy(U_out, U, sizeof(double) * NK * N);
+    free(num); free(cnt); free(Pd); free(ringsum); free(U); free(n_r);
     return 0;
 }

@@ -51,6 +51,14 @@ def lib():
         L.oracle_step_vjp.argtypes = common + [dp, dp, dp, dp, dp, dp, dp, dp, up]
         L.oracle_beta_grad.restype = C.c_int
         L.oracle_beta_grad.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.oracle_ring_of.restype = C.c_int
+        L.oracle_ring_of.argtypes = [C.c_int] * 4
+        L.oracle_ring_sizes.restype = None
+        L.oracle_ring_sizes.argtypes = [C.c_int, C.c_int, dp]
+        L.oracle_ring_step.restype = C.c_int
+        L.oracle_ring_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, C.c_int, C.c_int,
+                                       C.c_double, C.c_double, C.c_int, C.c_double, dp, dp, dp, dp,
+                                       dp, up, up]
         _lib = L
     return _lib
 
@@ -86,7 +94,7 @@ class Desc:
 
     def __init__(self, H, W, n_channels, n_kernels, src, dst, R, n_shells, beta, dt,
                  localized, genotype_update, m=None, s=None, h=None, eps=0.01,
-                 r_diff=1, tau=1e-5):
+                 r_diff=1, tau=1e-5, n_ring=0):
         self.H, self.W, self.C, self.NK = int(H), int(W), int(n_channels), int(n_kernels)
         self.src = np.ascontiguousarray(src, np.int32)
         self.dst = np.ascontiguousarray(dst, np.int32)
@@ -101,13 +109,14 @@ class Desc:
         self.s = _d(s if s is not None else z)
         self.h = _d(h if h is not None else z)
         self.eps, self.r_diff, self.tau = float(eps), int(r_diff), float(tau)
+        self.n_ring = int(n_ring)   # > 0: ring-decomposed kernels from the genes (ring_step)
         self.K = _d(kernels(self.R, self.n_shells, self.beta))
 
     @classmethod
     def from_world(cls, w, tau=1e-5):
         return cls(w.H, w.W, w.n_channels, w.n_kernels, w.src, w.dst, w.R, w.n_shells,
                    w.beta, w.dt, w.localized, w.genotype_update, w.m, w.s, w.h,
-                   w.eps, w.r_diff, tau)
+                   w.eps, w.r_diff, tau, getattr(w, "n_ring", 0))
 
     def _args(self):
         return [self.H, self.W, self.C, self.NK, _p(self.src, C.c_int), _p(self.dst, C.c_int),
@@ -171,6 +180,48 @@ def beta_grad(R: int, B: int, beta, gK) -> np.ndarray:
     if rc != 0:
         raise MemoryError("oracle_beta_grad failed")
     return out
+
+
+def ring_of(R: int, n_ring: int, dy: int, dx: int) -> int:
+    """Ring index of an offset (Section 2.4), -1 outside |d| < R."""
+    return lib().oracle_ring_of(R, n_ring, dy, dx)
+
+
+def ring_sizes(R: int, n_ring: int) -> np.ndarray:
+    """Number of lattice offsets in each ring."""
+    out = np.zeros(n_ring)
+    lib().oracle_ring_sizes(R, n_ring, _p(out))
+    return out
+
+
+def ring_step(d: Desc, A, P):
+    """One step with ring-decomposed localized kernels (Section 2.4): genes
+    P[9][NK][H][W] in the order r1, w1, b1, r2, w2, b2, m, s, h.  Returns
+    dict(A, P, U, alpha, amb) as float64 / uint8 arrays."""
+    if d.n_ring <= 0:
+        raise ValueError("ring_step needs n_ring > 0")
+    A = _d(A).reshape(d.C, d.H, d.W)
+    Pin = _d(P).reshape(9, d.NK, d.H, d.W)
+    A1 = np.empty_like(A)
+    P1 = np.empty_like(Pin)
+    U = np.empty((d.NK, d.H, d.W))
+    alpha = np.empty((d.H, d.W), np.uint8)
+    amb = np.empty((d.H, d.W), np.uint8)
+    rc = lib().oracle_ring_step(d.H, d.W, d.C, d.NK, _p(d.src, C.c_int), _p(d.dst, C.c_int), d.R,
+                                d.n_ring, d.dt, d.eps, d.r_diff, d.tau, _p(A), _p(Pin), _p(A1),
+                                _p(P1), _p(U), _p(alpha, C.c_uint8), _p(amb, C.c_uint8))
+    if rc != 0:
+        raise MemoryError("oracle_ring_step failed")
+    return dict(A=A1, P=P1, U=U, alpha=alpha, amb=amb)
+
+
+def ring_rollout(d: Desc, A, P, steps: int):
+    A = _d(A)
+    P = _d(P)
+    for _ in range(steps):
+        r = ring_step(d, A, P)
+        A, P = r["A"], r["P"]
+    return A, P
 
 
 def threads() -> int:

@@ -41,6 +41,11 @@ KERNEL_SRC_3CH = (0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 2)
 KERNEL_DST_3CH = (0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 2, 0, 2, 0, 1)
 
 GENE_RANGES = {"m": (0.1, 0.4), "s": (0.01, 0.1), "h": (0.0, 1.0)}
+# Kernel-function genes of the ring form (two bumps per kernel; the paper gives
+# no ranges): an inner and an outer bump, heights above the cutoff.
+RING_GENE_RANGES = {"r1": (0.15, 0.45), "w1": (0.05, 0.15), "b1": (0.3, 1.0),
+                    "r2": (0.5, 0.85), "w2": (0.05, 0.15), "b2": (0.1, 1.0)}
+RING_PARAMS = ("r1", "w1", "b1", "r2", "w2", "b2", "m", "s", "h")
 BLOB = 24
 C4_SIDES = (128, 192, 256, 384, 512, 768, 1024)
 
@@ -69,6 +74,9 @@ class World:
     P: Optional[np.ndarray]       # float32 [3, k, H, W] (m, s, h planes)
     target: Optional[np.ndarray] = None
     name: str = ""
+    n_ring: int = 0               # > 0: ring-decomposed kernels whose bump genes
+                                  # are localized too; P is then float32
+                                  # [9, k, H, W] (r1, w1, b1, r2, w2, b2, m, s, h)
 
     @property
     def cells(self) -> int:
@@ -152,6 +160,58 @@ def localized_world(rng: np.random.Generator, H: int, W: int, n_blobs: int,
                  dst=KERNEL_DST_3CH, R=R, n_shells=n_shells, beta=beta, dt=dt,
                  localized=1, genotype_update=genotype_update, m=None, s=None,
                  h=None, eps=0.01, r_diff=1, A=A, P=P, target=target, name=name)
+
+
+def ring_world(rng: np.random.Generator, H: int, W: int, n_blobs: int,
+               per_blob_genes: bool = False, R: int = 12, n_ring: int = 24,
+               dt: float = 0.2, name: str = "", sigma: Optional[float] = None) -> World:
+    """3-channel, 15-kernel world with ring-decomposed kernels: every one of
+    the 9 gene types (r1, w1, b1, r2, w2, b2, m, s, h) is a smoothed field per
+    kernel, drawn in that order, then uniform blobs as in localized_world."""
+    sig = default_sigma(H, W) if sigma is None else sigma
+    nk = 15
+    n_shells, beta = _draw_shells(rng, nk)   # unused by the ring form; drawn to keep the stream layout
+    ranges = dict(RING_GENE_RANGES, **GENE_RANGES)
+    P = np.empty((9, nk, H, W), np.float32)
+    for pi, p in enumerate(RING_PARAMS):
+        lo, hi = ranges[p]
+        for k in range(nk):
+            P[pi, k] = smooth_uniform_field(rng, H, W, lo, hi, sig)
+    A = np.zeros((3, H, W), np.float32)
+    corners = []
+    for _ in range(n_blobs):
+        y0 = int(rng.integers(H))
+        x0 = int(rng.integers(W))
+        vals = rng.random((3, BLOB, BLOB)).astype(np.float32)
+        _stamp(A, vals, y0, x0)
+        corners.append((y0, x0))
+    if per_blob_genes:
+        side = 2 * BLOB
+        for (y0, x0) in corners:
+            genes = np.empty((9, nk), np.float32)
+            for pi, p in enumerate(RING_PARAMS):
+                lo, hi = ranges[p]
+                genes[pi] = (lo + (hi - lo) * rng.random(nk)).astype(np.float32)
+            block = np.broadcast_to(genes[:, :, None, None], (9, nk, side, side))
+            _stamp(P, block, y0 + BLOB // 2 - side // 2, x0 + BLOB // 2 - side // 2)
+    return World(H=H, W=W, n_channels=3, n_kernels=nk, src=KERNEL_SRC_3CH,
+                 dst=KERNEL_DST_3CH, R=R, n_shells=n_shells, beta=beta, dt=dt,
+                 localized=1, genotype_update=1, m=None, s=None, h=None, eps=0.01,
+                 r_diff=1, A=A, P=P, name=name, n_ring=n_ring)
+
+
+def ring_test_world(H: int, W: int, seed: int, n_blobs: Optional[int] = None) -> World:
+    """A small ring-form world for parity tests (blob density of the 512 case)."""
+    rng = np.random.default_rng(seed)
+    nb = blobs_for_side(int(np.sqrt(H * W))) if n_blobs is None else n_blobs
+    return ring_world(rng, H, W, nb, name=f"ring-{H}x{W}-s{seed}")
+
+
+def config_ring(H: int = 4096, W: int = 4096, n_blobs: int = 2000) -> World:
+    """The 4096x4096 workload (2000 blobs with their own genes) with
+    ring-decomposed kernels: 24 rings of the R = 12 disk."""
+    rng = np.random.default_rng(SEED_BASE + 6)
+    return ring_world(rng, H, W, n_blobs, per_blob_genes=True, name=f"lenia-ring-3ch15k-{H}")
 
 
 def orbium_like_world(seed: Optional[int] = None, H: int = 64, W: int = 64,
