@@ -25,6 +25,8 @@
  * Layouts (all row-major FP32, device memory, 4-byte aligned):
  *   A  float[C][H][W]             cell states
  *   P  float[3][NK][H][W]         gene planes m (k = 0..NK-1), then s, then h
+ *      float[9][NK][H][W]         with n_ring > 0: r1, w1, b1, r2, w2, b2, m, s, h
+ *                                 (the two kernel-function bumps, then growth)
  * Ownership: the caller owns every state, gene, gradient and `saved` buffer;
  * a plan owns its workspaces and tables and frees them in lenia_plan_destroy.
  * Streams: every call only enqueues work on `stream` (a hipStream_t, NULL =
@@ -97,6 +99,21 @@ typedef struct {
     int32_t tile_y, tile_x;     /* output tile of the fused step kernel; 0,0 =
                                    the autotuned / default choice                */
     uint32_t flags;             /* LENIA_FLAG_*                                  */
+    int32_t n_ring;             /* 0: the ring-shell kernels above (beta, shells);
+                                   > 0: ring-decomposed kernels with localized
+                                   kernel genes (Section 2.4): the disk |d| < R
+                                   split into n_ring rings, ring j = the offsets
+                                   with floor(n_ring |d| / R) = j, weighted per
+                                   cell by the two bumps b exp(-(j/n_ring -
+                                   r)^2 / (2 w^2)) of each kernel's genes; then
+                                   u_k = sum_j kw_j (ring-j sum of A_src) /
+                                   sum_j kw_j (ring-j size), 0 if that is 0.
+                                   Needs localized and genotype_update; P has 9
+                                   gene types (below); n_shells / beta unused
+                                   (may be NULL).  Compiled: 3 channels / 15
+                                   kernels, R = 12, n_ring = 24, lenia_step
+                                   only (no saved buffer, batched plan,
+                                   potentials, adjoint, autotune, DFT form).  */
 } lenia_desc;
 
 #define LENIA_FLAG_AUTOTUNE 1u  /* time the tile candidates at plan time and

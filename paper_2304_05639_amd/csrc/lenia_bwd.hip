@@ -641,6 +641,8 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
     try {
         if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
         if (p->batched) return set_error(LENIA_ERR_STATE, "adjoint needs a single-world plan");
+        if (p->rings)
+            return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint for ring-decomposed kernels");
         WorldPlan& w = p->worlds[0];
         if (w.mode == MODE_GLOBAL)
             return set_error(LENIA_ERR_UNSUPPORTED, "adjoint needs localized genes");

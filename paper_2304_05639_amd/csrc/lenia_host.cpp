@@ -127,13 +127,16 @@ lenia_status validate(const lenia_desc* d)
         return fail(LENIA_ERR_INVALID_ARG, "n_channels must be in [1, 3]");
     if (d->n_kernels < 1 || d->n_kernels > LENIA_MAX_KERNELS)
         return fail(LENIA_ERR_INVALID_ARG, "n_kernels must be in [1, 15]");
-    if (!d->src || !d->dst || !d->n_shells || !d->beta)
+    if (d->n_ring < 0) return fail(LENIA_ERR_INVALID_ARG, "n_ring must be >= 0");
+    const bool rings = (d->n_ring > 0);
+    if (!d->src || !d->dst || (!rings && (!d->n_shells || !d->beta)))
         return fail(LENIA_ERR_INVALID_ARG, "src, dst, n_shells and beta must be non-NULL");
     for (int k = 0; k < d->n_kernels; ++k) {
         if (d->src[k] < 0 || d->src[k] >= d->n_channels || d->dst[k] < 0 ||
             d->dst[k] >= d->n_channels)
             return fail(LENIA_ERR_INVALID_ARG, "kernel " + std::to_string(k) +
                                                    ": src/dst channel out of range");
+        if (rings) continue;   // kernels come from the genes
         if (d->n_shells[k] < 1 || d->n_shells[k] > LENIA_MAX_SHELLS)
             return fail(LENIA_ERR_INVALID_ARG, "kernel " + std::to_string(k) +
                                                    ": n_shells must be in [1, 3]");
@@ -143,7 +146,7 @@ lenia_status validate(const lenia_desc* d)
                                                        ": shell heights must be finite and >= 0");
     }
     if (d->R < 1) return fail(LENIA_ERR_INVALID_ARG, "R must be >= 1");
-    for (int k = 0; k < d->n_kernels; ++k)
+    for (int k = 0; k < d->n_kernels && !rings; ++k)
         if (!(raw_kernel_sum(d->R, d->n_shells[k], d->beta + 3 * k) > 0.0))
             return fail(LENIA_ERR_INVALID_ARG,
                         "kernel " + std::to_string(k) + " is identically zero (cannot normalize)");
@@ -172,6 +175,9 @@ lenia_status validate(const lenia_desc* d)
     if ((d->tile_y == 0) != (d->tile_x == 0) || d->tile_y < 0 || d->tile_x < 0)
         return fail(LENIA_ERR_INVALID_ARG, "tile_y and tile_x must both be 0 or both > 0");
     if (d->flags & ~LENIA_FLAG_AUTOTUNE) return fail(LENIA_ERR_INVALID_ARG, "unknown flags");
+    if (rings && !(d->localized && d->genotype_update))
+        return fail(LENIA_ERR_INVALID_ARG, "ring-decomposed kernels need localized genes with "
+                                           "genotype_update");
 
     // what the compiled kernels cover
     const int table = table_of(d);
@@ -182,6 +188,18 @@ lenia_status validate(const lenia_desc* d)
                     "1->0, 1->2, 2->0, 2->1)");
     if (d->genotype_update && d->r_diff != 1)
         return fail(LENIA_ERR_UNSUPPORTED, "only r_diff = 1 is compiled in");
+    if (rings) {
+        if (table != TABLE_3x15 || d->R != 12 || d->n_ring != 24)
+            return fail(LENIA_ERR_UNSUPPORTED, "ring-decomposed kernels are compiled for 3 channels "
+                                               "/ 15 kernels, R = 12 and n_ring = 24");
+        if (d->conv != LENIA_CONV_AUTO && d->conv != LENIA_CONV_DIRECT_F32)
+            return fail(LENIA_ERR_UNSUPPORTED, "ring-decomposed kernels use the direct form");
+        if (d->flags & LENIA_FLAG_AUTOTUNE)
+            return fail(LENIA_ERR_UNSUPPORTED, "no autotuning for ring-decomposed kernels");
+        if (d->tile_y && !(d->tile_y == 8 && d->tile_x == 32))
+            return fail(LENIA_ERR_UNSUPPORTED, "ring-decomposed kernels run 8 x 32 tiles");
+        return LENIA_OK;
+    }
     if (d->conv != LENIA_CONV_AUTO && d->conv != LENIA_CONV_DIRECT_F32 &&
         !conv_form_supported(d->conv, table, d->R))
         return fail(LENIA_ERR_UNSUPPORTED, "conv form not available for this table / R");

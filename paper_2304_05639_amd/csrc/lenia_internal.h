@@ -124,6 +124,8 @@ typedef hipError_t (*step_launch_fn)(const WorldArgs& w, int mode, hipStream_t s
 typedef hipError_t (*batch_launch_fn)(const BatchList& b, int mode, hipStream_t s);
 
 step_launch_fn find_step_launcher(int table, int R, int ty, int tx);
+// the ring-decomposed kernel form (genes P[9][NK][H][W]); null if not compiled
+step_launch_fn find_ring_step_launcher(int table, int R, int ty, int tx);
 batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx);
 // candidate tiles compiled for (table, R); returns count, fills up to max pairs
 int step_tile_candidates(int table, int R, int* ty, int* tx, int max);

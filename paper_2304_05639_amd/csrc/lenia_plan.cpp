@@ -94,6 +94,15 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
     w.mode = mode_of(d);
     w.dt = d->dt;
     w.eps = d->eps;
+    w.table = p->table;
+    lenia_status st;
+    if (d->n_ring > 0) {
+        // ring-decomposed kernels: the weights come from the genes in the
+        // kernel, no tables; 9 gene types per kernel
+        w.gene_types = 9;
+        if ((st = dmalloc(p, (void**)&w.ws_A, w.a_elems() * sizeof(float))) != LENIA_OK) return st;
+        return dmalloc(p, (void**)&w.ws_P, w.p_elems() * sizeof(float));
+    }
     w.n_shells.assign(d->n_shells, d->n_shells + w.NK);
     w.beta.assign(d->beta, d->beta + 3 * w.NK);
     if (!d->localized) {
@@ -132,7 +141,6 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
     }
     // the same weights ordered (orbit, source channel, slot of the kernel among
     // the kernels reading that channel), 8 slots per source
-    w.table = p->table;
     const int kps = (p->table == TABLE_3x15) ? Table3x15::KPS : Table1x1::KPS;
     // orbit order of the step kernel's loops: axis (a,0), diagonal (a,a),
     // then general (a,b) with 0 < b < a, each by increasing a (then b)
@@ -156,7 +164,6 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
                 const int k = (p->table == TABLE_3x15) ? Table3x15::kidx[sc][j] : Table1x1::kidx[sc][j];
                 hwt[((size_t)i * w.C + sc) * 8 + j] = hw[(size_t)k * NO + korder[i]];
             }
-    lenia_status st;
     if ((st = dmalloc(p, (void**)&w.d_wt, hwt.size() * sizeof(float))) != LENIA_OK) return st;
     {
         float* keep_t = new float[hwt.size()];
@@ -396,6 +403,13 @@ static void default_tile(lenia_plan_t p)
 static lenia_status finish_tile_choice(lenia_plan_t p, const lenia_desc* d, hipStream_t s)
 {
     lenia_status st = LENIA_OK;
+    if (p->rings) {
+        p->tile_y = 8;
+        p->tile_x = 32;
+        p->step_fn = find_ring_step_launcher(p->table, p->R, p->tile_y, p->tile_x);
+        if (!p->step_fn) return set_error(LENIA_ERR_UNSUPPORTED, "ring form not compiled in");
+        return LENIA_OK;
+    }
     if (d->tile_y) {
         p->tile_y = d->tile_y;
         p->tile_x = d->tile_x;
@@ -433,6 +447,9 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
                              "worlds of a batched plan must share kernel table, gene mode and R");
     if (ds[0].conv != LENIA_CONV_AUTO && ds[0].conv != LENIA_CONV_DIRECT_F32 && batched)
         return set_error(LENIA_ERR_UNSUPPORTED, "batched plans use the direct FP32 form");
+    for (int i = 0; i < n; ++i)
+        if (ds[i].n_ring > 0 && batched)
+            return set_error(LENIA_ERR_UNSUPPORTED, "ring-decomposed kernels run single-world plans");
     hipStream_t s = (hipStream_t)stream;
     lenia_plan_t p = new (std::nothrow) lenia_plan_;
     if (!p) return set_error(LENIA_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -441,6 +458,7 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     p->table = table;
     p->mode = mode;
     p->R = ds[0].R;
+    p->rings = (ds[0].n_ring > 0);
     p->conv = (ds[0].conv == LENIA_CONV_AUTO) ? LENIA_CONV_DIRECT_F32 : ds[0].conv;
     p->worlds.resize(n);
     std::vector<void*> keep;
@@ -532,7 +550,7 @@ lenia_status lenia_plan_destroy(lenia_plan_t p)
 
 size_t lenia_saved_bytes(lenia_plan_t p)
 {
-    if (!p || p->batched) return 0;
+    if (!p || p->batched || p->rings) return 0;
     const WorldPlan& w = p->worlds[0];
     const size_t u = (size_t)w.NK * w.cells() * sizeof(float);
     return u + ((w.cells() + 255) / 256) * 256;
@@ -569,6 +587,8 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
         if (p->batched) return set_error(LENIA_ERR_STATE, "batched plan: use lenia_step_batched");
         if (n_steps < 0) return set_error(LENIA_ERR_INVALID_ARG, "n_steps < 0");
         if (saved && n_steps != 1) return set_error(LENIA_ERR_INVALID_ARG, "saved needs n_steps == 1");
+        if (saved && p->rings)
+            return set_error(LENIA_ERR_UNSUPPORTED, "no saved buffer for ring-decomposed kernels");
         WorldPlan& w = p->worlds[0];
         if (!A_in || !A_out) return set_error(LENIA_ERR_INVALID_ARG, "A_in / A_out is NULL");
         if (((uintptr_t)A_in | (uintptr_t)A_out) & 3)
@@ -657,6 +677,9 @@ lenia_status lenia_potentials(lenia_plan_t p, const float* A, float* U, void* st
     try {
         if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
         if (p->batched) return set_error(LENIA_ERR_STATE, "batched plan");
+        if (p->rings)
+            return set_error(LENIA_ERR_UNSUPPORTED,
+                             "ring-decomposed potentials depend on the genes: not available");
         if (!A || !U) return set_error(LENIA_ERR_INVALID_ARG, "A / U is NULL");
         if (((uintptr_t)A | (uintptr_t)U) & 3)
             return set_error(LENIA_ERR_INVALID_ARG, "buffers must be 4-byte aligned");

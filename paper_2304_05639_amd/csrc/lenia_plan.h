@@ -38,6 +38,7 @@ struct WorldPlan {
     std::vector<double> gm, gs, gh;
     int n_orbits = 0;
     int table = 0;
+    int gene_types = 3;            // gene planes per kernel: 3 (m, s, h) or 9 (ring form)
     float* d_w = nullptr;          // [NK][n_orbits] orbit weights of K~_k
     float* d_wt = nullptr;         // [n_orbits][C][8] by (orbit, source, slot)
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
@@ -50,10 +51,10 @@ struct WorldPlan {
     float* dft_khat = nullptr;
     float* dft_u = nullptr;        // [NK][H][W]
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
-    float* ws_P = nullptr;         // [3][NK][H][W] (gene update only)
+    float* ws_P = nullptr;         // [gene_types][NK][H][W] (gene update only)
     size_t cells() const { return (size_t)H * W; }
     size_t a_elems() const { return (size_t)C * H * W; }
-    size_t p_elems() const { return (size_t)3 * NK * H * W; }
+    size_t p_elems() const { return (size_t)gene_types * NK * H * W; }
     WorldArgs args_template() const;
 };
 
@@ -74,6 +75,7 @@ struct lenia_plan_ {
     std::vector<lenia::WorldPlan> worlds;
     bool batched = false;
     int table = 0, mode = 0, R = 0, conv = LENIA_CONV_DIRECT_F32;
+    bool rings = false;            // ring-decomposed kernels (n_ring > 0)
     int tile_y = 0, tile_x = 0;
     lenia::step_launch_fn step_fn = nullptr;
     lenia::batch_launch_fn batch_fn = nullptr;

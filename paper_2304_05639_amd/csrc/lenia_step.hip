@@ -260,7 +260,7 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 // first cell in the staged tile (channel 0); cells past the torus edge are
 // skipped.  Planes are the outer loop, so each plane's descriptor is used for
 // all the cells and then dropped.
-template <class T, int Q, class L>
+template <class T, int Q, class L, int NPG>
 __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const float* c, int gy, int gx)
 {
     const size_t HW = (size_t)wd.H * wd.W;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
             if (in[q]) pst(pl, ob[q], clip01(c[ch * L::CHS + q * L::RS]));
     }
 #pragma unroll
-    for (int p = 0; p < 3 * T::NK; ++p) {
+    for (int p = 0; p < NPG; ++p) {
         const plane_t pl = plane(wd.P_out + (size_t)p * HW, pb);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
@@ -290,6 +290,191 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (in[q]) wd.alpha_save[ob[q] >> 2] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ring-decomposed localized kernels (Section 2.4).  The disk |d| < R is split
+// into NR = 2R rings, ring j holding the offsets with floor(NR |d| / R) = j.
+// Each kernel's two bumps (r_i, w_i, b_i) are genes of the cell, and
+//   u_k = sum_j kw_j S_j / sum_j kw_j n_j,
+//   kw_j = sum_i b_i exp(-(j/NR - r_i)^2 / (2 w_i^2)),
+// with S_j the sum of the source channel over ring j and n_j its offset count.
+// Every orbit of the lattice symmetries lies in one ring, so the ring sums come
+// from the same orbit walk as the cast kernels' potentials.  Genes P[9][NK]
+// in the order r1, w1, b1, r2, w2, b2, m, s, h.
+// ---------------------------------------------------------------------------
+struct RingOrbit {
+    int a, b, ring;   // representative offset (a, b), 0 <= b <= a
+};
+
+// floor(NR sqrt(d2) / R) in integers
+constexpr int ring_of_d2(int R, int NR, int d2)
+{
+    int j = 0;
+    while ((j + 1) * (j + 1) * R * R <= NR * NR * d2) ++j;
+    return j;
+}
+
+template <int R>
+struct RingTables {
+    static constexpr int NR = 2 * R;
+    static constexpr int NO = [] {
+        int n = 0;
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a * a + b * b < R * R) ++n;
+        return n;
+    }();
+    RingOrbit orb[NO];    // in ring order (centre first)
+    int slot[NR];         // ring -> index among the non-empty rings, or -1
+    int ring_of_slot[NR];
+    int size_of_slot[NR];
+    int nre;              // number of non-empty rings
+};
+
+template <int R>
+constexpr RingTables<R> make_ring_tables()
+{
+    RingTables<R> t{};
+    constexpr int NR = RingTables<R>::NR;
+    int size[NR] = {};
+    for (int dy = -R; dy <= R; ++dy)
+        for (int dx = -R; dx <= R; ++dx)
+            if (dy * dy + dx * dx < R * R) ++size[ring_of_d2(R, NR, dy * dy + dx * dx)];
+    t.nre = 0;
+    for (int j = 0; j < NR; ++j) {
+        t.slot[j] = -1;
+        if (size[j] > 0) {
+            t.slot[j] = t.nre;
+            t.ring_of_slot[t.nre] = j;
+            t.size_of_slot[t.nre] = size[j];
+            ++t.nre;
+        }
+    }
+    int n = 0;
+    for (int j = 0; j < NR; ++j)
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b <= a; ++b)
+                if (a * a + b * b < R * R && ring_of_d2(R, NR, a * a + b * b) == j) t.orb[n++] = {a, b, j};
+    return t;
+}
+
+template <int R>
+inline constexpr RingTables<R> kRings = make_ring_tables<R>();
+
+// Adds orbit I (and, recursively, the following ones) of the ring walk into
+// the ring sums S[slot][channel] of the cell at c.
+template <class T, class L, int R, int I>
+__device__ __forceinline__ void ring_walk(float (&S)[kRings<R>.nre][T::C], const float* c)
+{
+    if constexpr (I < RingTables<R>::NO) {
+        constexpr RingOrbit o = kRings<R>.orb[I];
+        constexpr int sl = kRings<R>.slot[o.ring];
+        constexpr int RS = L::RS, ES = L::ES;
+        float sum[1][T::C];
+        if constexpr (o.a == 0) {
+            tap_load<T, 1, L>(sum, c);
+        } else if constexpr (o.b == 0) {
+            quad_sum<T, 1, L>(sum, c + o.a * RS, c - o.a * RS, c + o.a * ES, c - o.a * ES);
+        } else if constexpr (o.b == o.a) {
+            quad_sum<T, 1, L>(sum, c + o.a * (RS + ES), c + o.a * (RS - ES), c - o.a * (RS - ES),
+                              c - o.a * (RS + ES));
+        } else {
+            float s0[1][T::C], s1[1][T::C];
+            quad_sum<T, 1, L>(s0, c + o.a * RS + o.b * ES, c + o.a * RS - o.b * ES,
+                              c - o.a * RS + o.b * ES, c - o.a * RS - o.b * ES);
+            quad_sum<T, 1, L>(s1, c + o.b * RS + o.a * ES, c + o.b * RS - o.a * ES,
+                              c - o.b * RS + o.a * ES, c - o.b * RS - o.a * ES);
+#pragma unroll
+            for (int ch = 0; ch < T::C; ++ch) sum[0][ch] = s0[0][ch] + s1[0][ch];
+        }
+#pragma unroll
+        for (int ch = 0; ch < T::C; ++ch) S[sl][ch] += sum[0][ch];
+        ring_walk<T, L, R, I + 1>(S, c);
+    }
+}
+
+// Gene diffusion, ring weights, potentials, alpha, growth and update of one
+// cell in the ring form.  The kernels are taken source channel by source
+// channel (the ring sums of channel c serve its kernels); each kernel's 9 gene
+// planes are diffused and stored, and a lane stops working on further kernels
+// once its alpha has failed.  Where alpha = 0 at the end, A' = clip01(A) and
+// every gene plane is overwritten with 0.
+template <class T, int R>
+__device__ __forceinline__ void ring_epilogue_cell(const WorldArgs& wd, const float (&S)[kRings<R>.nre][T::C],
+                                                   const float (&a)[T::C], int gy, int gx)
+{
+    constexpr int NK = T::NK, NPG = 9 * NK, NRE = kRings<R>.nre, NR = RingTables<R>::NR;
+    const int H = wd.H, W = wd.W;
+    const size_t HW = (size_t)H * W;
+    const uint32_t ob = 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx);
+    const uint32_t pb = 4u * (uint32_t)HW;
+    const float eps = wd.eps, cs = wd.cnt_scale, ncs = wd.cnt_bias;
+    const NbrB nb = neighbour_bytes(gy, gx, H, W);
+    bool alpha = true;
+    float sum[T::C];
+#pragma unroll
+    for (int ch = 0; ch < T::C; ++ch) sum[ch] = 0.f;
+#pragma unroll
+    for (int c = 0; c < T::C; ++c) {
+#pragma unroll 1
+        for (int j = 0; j < T::KPS; ++j) {
+            if (!alpha) continue;
+            const int k = T::kidx[c][j];
+            // the kernel's 9 genes, diffused (Section 2.3), in groups of three
+            // planes with the next group's reads in flight
+            float g[9];
+            float v[2][3][5];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) load_disk(v[0][i], plane(wd.P + (size_t)(i * NK + k) * HW, pb), nb);
+#pragma unroll
+            for (int grp = 0; grp < 3; ++grp) {
+                if (grp + 1 < 3) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        load_disk(v[(grp + 1) & 1][i],
+                                  plane(wd.P + (size_t)(((grp + 1) * 3 + i) * NK + k) * HW, pb), nb);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int q = grp * 3 + i;
+                    g[q] = diffuse_disk(v[grp & 1][i], cs, ncs);
+                    alpha = alpha && (g[q] > eps);
+                    pst(plane(wd.P_out + (size_t)(q * NK + k) * HW, pb), ob, g[q]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (!alpha) continue;
+            // ring weights of the two bumps: b exp2(c (x - r)^2), c = -log2(e) / (2 w^2)
+            const float c1 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[1] * g[1]);
+            const float c2 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[4] * g[4]);
+            float num = 0.f, den = 0.f;
+#pragma unroll
+            for (int sl = 0; sl < NRE; ++sl) {
+                constexpr float inv_nr = 1.0f / (float)NR;
+                const float x = (float)kRings<R>.ring_of_slot[sl] * inv_nr;
+                const float d1 = x - g[0], d2 = x - g[3];
+                const float kw = g[2] * __builtin_amdgcn_exp2f(c1 * (d1 * d1)) +
+                                 g[5] * __builtin_amdgcn_exp2f(c2 * (d2 * d2));
+                num = fmaf(kw, S[sl][c], num);
+                den = fmaf(kw, (float)kRings<R>.size_of_slot[sl], den);
+            }
+            const float u = (den > 0.f) ? num / den : 0.f;
+            alpha = alpha && (u > eps);
+            const float gk = growth(u, g[6], g[7], g[8]);
+            const int dk = T::dst[k];
+#pragma unroll
+            for (int ch = 0; ch < T::C; ++ch) sum[ch] += (dk == ch) ? gk : 0.f;
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < T::C; ++ch)
+        pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(alpha ? a[ch] + wd.dt * sum[ch] : a[ch]));
+    if (!alpha) {
+#pragma unroll
+        for (int q = 0; q < NPG; ++q) pst(plane(wd.P_out + (size_t)q * HW, pb), ob, 0.f);
     }
 }
 
@@ -306,11 +491,12 @@ template <class T, int R, int TY, int TX>
 constexpr int tile_lds_floats() { return TileLayout<T, R, TY, TX>::floats; }
 
 // One tile of one world.  Each thread owns Q vertically adjacent cells.
-template <class T, int R, int TY, int TX>
+template <class T, int R, int TY, int TX, bool RINGS = false>
 __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA,
                                              int* tile_flag)
 {
     using L = TileLayout<T, R, TY, TX>;
+    constexpr int NPG = (RINGS ? 9 : 3) * T::NK;   // gene planes
     constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
     constexpr int NK = T::NK;
     constexpr int NT = step_threads<TY, TX>();
@@ -417,8 +603,8 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             // an empty channel or a dead gene plane: alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
-            write_dead_cells<T, Q, L>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
-                                      x0 + lx);
+            write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
+                                           x0 + lx);
             return;
         }
     }
@@ -429,6 +615,27 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy >= H || gx >= W) return;
     const float* c = sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES;
+    if constexpr (RINGS) {
+        static_assert(Q == 1 && L::interleaved, "the ring form runs one cell per thread, 3 channels");
+        float S[kRings<R>.nre][T::C];
+#pragma unroll
+        for (int sl = 0; sl < kRings<R>.nre; ++sl)
+#pragma unroll
+            for (int ch = 0; ch < T::C; ++ch) S[sl][ch] = 0.f;
+        ring_walk<T, L, R, 0>(S, c);
+        // materialize every ring sum here: otherwise the compiler sinks the sums
+        // of channels 1 and 2 to their first use after channel 0's kernels and
+        // keeps all their tap values live (and spilled) until then
+#pragma unroll
+        for (int sl = 0; sl < kRings<R>.nre; ++sl)
+#pragma unroll
+            for (int ch = 0; ch < T::C; ++ch) asm volatile("" : "+v"(S[sl][ch]));
+        float a[T::C];
+#pragma unroll
+        for (int ch = 0; ch < T::C; ++ch) a[ch] = c[ch * L::CHS];
+        ring_epilogue_cell<T, R>(wd, S, a, gy, gx);
+        return;
+    }
     float u[Q][NK];
     conv_cells<T, Q, R, L>(c, (cfloat*)wd.wt, u);
     if (mode == MODE_POTENTIALS) {
@@ -458,6 +665,29 @@ __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void ste
     __shared__ __attribute__((aligned(16))) float sA[tile_lds_floats<T, R, TY, TX>()];
     __shared__ int tile_flag;
     process_tile<T, R, TY, TX>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA, &tile_flag);
+}
+
+// Step with ring-decomposed localized kernels (genes P[9][NK][H][W]).
+template <class T, int R, int TY, int TX>
+__global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void ring_step_kernel(WorldArgs wd, int mode)
+{
+    __shared__ __attribute__((aligned(16))) float sA[tile_lds_floats<T, R, TY, TX>()];
+    __shared__ int tile_flag;
+    process_tile<T, R, TY, TX, true>(wd, xcd_tile(blockIdx.x, gridDim.x), mode, sA, &tile_flag);
+}
+
+template <class T, int R, int TY, int TX>
+hipError_t launch_ring_step(const WorldArgs& w, int mode, hipStream_t s)
+{
+    hipLaunchKernelGGL((ring_step_kernel<T, R, TY, TX>), dim3(w.n_tiles), dim3(step_threads<TY, TX>()), 0, s,
+                       w, mode);
+    return hipGetLastError();
+}
+
+step_launch_fn find_ring_step_launcher(int table, int R, int ty, int tx)
+{
+    if (table == TABLE_3x15 && R == 12 && ty == 8 && tx == 32) return &launch_ring_step<Table3x15, 12, 8, 32>;
+    return nullptr;
 }
 
 // Epilogue of a step whose potentials were computed elsewhere (the MFMA DFT

@@ -40,7 +40,7 @@ class Desc(C.Structure):
                 ("m", C.POINTER(C.c_double)), ("s", C.POINTER(C.c_double)),
                 ("h", C.POINTER(C.c_double)), ("eps", C.c_double), ("r_diff", C.c_int32),
                 ("conv", C.c_int32), ("tile_y", C.c_int32), ("tile_x", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("n_ring", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -123,7 +123,7 @@ class DescBuilder:
                          int(w.R), ip(self._nsh), dp(self._beta), float(w.dt), int(w.localized),
                          int(w.genotype_update), dp(self._m), dp(self._s), dp(self._h),
                          float(w.eps), int(w.r_diff), int(conv), int(ty), int(tx),
-                         FLAG_AUTOTUNE if autotune else 0)
+                         FLAG_AUTOTUNE if autotune else 0, int(getattr(w, "n_ring", 0)))
 
 
 def validate(w, **kw) -> int:
@@ -181,6 +181,8 @@ class Plan:
                                            int(world.H), int(world.W))
         self.localized = int(world.localized)
         self.update = int(world.genotype_update)
+        # gene types per kernel: m, s, h, or the ring form's 9
+        self.gene_types = 9 if int(getattr(world, "n_ring", 0)) > 0 else 3
 
     @property
     def handle(self):
@@ -212,7 +214,7 @@ class Plan:
         import torch
         _check_tensor(A, (self.C, self.H, self.W), "A")
         if self.localized:
-            _check_tensor(P, (3, self.NK, self.H, self.W), "P")
+            _check_tensor(P, (self.gene_types, self.NK, self.H, self.W), "P")
         if A_out is None:
             A_out = torch.empty_like(A)
         if self.update and P_out is None:

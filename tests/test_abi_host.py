@@ -142,3 +142,22 @@ def test_missing_library_raises(tmp_path, monkeypatch):
             m2.lib()
     finally:
         importlib.reload(mod)
+
+
+def test_ring_form_descriptors():
+    w = inputs.ring_test_world(32, 32, seed=3, n_blobs=1)
+    assert _ok(w) == L.OK, L.last_error()
+    # the ring form takes its kernels from the genes: shell tables may be NULL
+    b = L.DescBuilder(w)
+    b.desc.n_shells = None
+    b.desc.beta = None
+    import ctypes
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK, L.last_error()
+    assert _ok(_mut(w, n_ring=-1)) == L.ERR_INVALID_ARG
+    assert _ok(_mut(w, genotype_update=0)) == L.ERR_INVALID_ARG
+    for changes in (dict(n_ring=12), dict(R=13, n_ring=26)):
+        assert _ok(_mut(w, **changes)) == L.ERR_UNSUPPORTED, changes
+    assert _ok(w, conv=L.CONV_DFT_SPLIT_BF16) == L.ERR_UNSUPPORTED
+    assert _ok(w, autotune=True) == L.ERR_UNSUPPORTED
+    assert _ok(w, tile=(16, 32)) == L.ERR_UNSUPPORTED
+    assert _ok(w, tile=(8, 32)) == L.OK
