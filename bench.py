@@ -7,6 +7,10 @@ full update of (A, P) through lenia_step; inputs are resident in HBM before
 the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Secondary legs in the same line: the split DFT forms on MFMA, the adjoint's
+backward/forward time ratio, the ring-decomposed kernel form (and, with
+--batched, the 256-world batched workload).
 """
 from __future__ import annotations
 
@@ -27,6 +31,10 @@ STEP_SRCS = [os.path.join(CSRC, f) for f in ("lenia_step.hip", "lenia_device.h",
 DFT_SRCS = [os.path.join(CSRC, f) for f in ("lenia_dft.hip", "lenia_device.h", "lenia_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_4096.json")
 DFT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dft_conv_4096.json")
+RING_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ring_step_4096.json")
+# ring-decomposed kernels (9 gene types per kernel): read A 12 + write A 12 +
+# read P 540 + write P 540 (FP32)
+RING_BYTES_PER_CELL = 1104
 
 
 def kernel_sha(srcs=STEP_SRCS) -> str:
@@ -183,6 +191,36 @@ def dft_form(world, steps: int = 20, warmup: int = 2, conv: int = 2):
             "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile"}
 
 
+def ring_form(steps: int = 20, warmup: int = 10):
+    """The 4096^2 workload with ring-decomposed kernels (24 rings, localized
+    kernel genes): full-step throughput against the HBM floor of its
+    algorithmic bytes."""
+    import torch
+    from paper_2304_05639_amd import inputs, lenia
+    world = inputs.config_ring()
+    cells = world.H * world.W
+    plan = lenia.Plan(world)
+    A = torch.tensor(world.A, device="cuda")
+    P = torch.tensor(world.P, device="cuda")
+    A2, P2 = torch.empty_like(A), torch.empty_like(P)
+    plan.step(A, P, A2, P2, n_steps=warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.step(A2, P2, A, P, n_steps=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    achieved = RING_BYTES_PER_CELL * cells / (ms / 1e3) / 1e9
+    return {"value": cells / (ms / 1e3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "steps": steps, "warmup": warmup,
+            "workload": "lenia-ring-3ch15k-4096x4096: 24 rings of the R = 12 disk, 9 gene types "
+                        "per kernel, 2000 blobs with their own genes",
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(cells, RING_TRAFFIC_FILE, STEP_SRCS)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,7 +233,9 @@ def main():
                          "split-bf16 DFT-as-GEMM form on MFMA")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-dft", action="store_true", help="skip the MFMA DFT-form leg")
-    ap.add_argument("--only", choices=["ratio", "batched", "dft"], default=None,
+    ap.add_argument("--no-ring", action="store_true",
+                    help="skip the ring-decomposed kernel leg (slow input generation)")
+    ap.add_argument("--only", choices=["ratio", "batched", "dft", "ring"], default=None,
                     help="run a single secondary leg (for profiling) and print its JSON")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB fill, copy and sum (reference kernels for the "
@@ -212,6 +252,15 @@ def main():
     import torch
     from paper_2304_05639_amd import inputs, lenia
 
+    if args.calibrate:
+        # reference kernels of known size for the HBM byte counters: a 1 GiB
+        # fill (writes), copy and sum (reads)
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        print(f"calibration sum {float(src.sum()):.0f}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        del src, dst
     if args.only == "ratio":
         print(json.dumps({"bwd_fwd_ratio": backward_forward_ratio(),
                           "bwd_fwd_ratio_dft": backward_forward_ratio(
@@ -219,6 +268,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched": batched_throughput()}), flush=True)
+        return
+    if args.only == "ring":
+        print(json.dumps({"ring_form": ring_form()}), flush=True)
         return
     world = inputs.config3()
     if args.only == "dft":
@@ -281,19 +333,14 @@ def main():
     if not args.no_dft and args.conv == "direct":
         out["dft_split_bf16"] = dft_form(world)
         out["dft_split_f16"] = dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)
-    if args.calibrate:
-        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        out["calibration_sum"] = float(src.sum())
-        torch.cuda.synchronize()
-        del src, dst
     if not args.no_backward:
         out["bwd_fwd_ratio"] = backward_forward_ratio()
         if not args.no_dft:
             out["bwd_fwd_ratio_dft"] = backward_forward_ratio(conv=lenia.CONV_DFT_SPLIT_BF16)
     if args.batched:
         out["batched"] = batched_throughput()
+    if not args.no_ring:
+        out["ring_form"] = ring_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(world)
     print(json.dumps(out), flush=True)
