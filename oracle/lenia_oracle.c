@@ -28,7 +28,9 @@
  *   - diffusion disk |d| <= r_diff inclusive; output 0 where the count is 0;
  *   - thresholds are strict (> eps); only the m, s, h genes are localized.
  * The ring-decomposed kernels of Section 2.4, whose kernel genes are localized
- * too, are a second step function, oracle_ring_step, at the end of the file.
+ * too, are a second step function, oracle_ring_step; the walls, mutation and
+ * penalization operators of Sections 2.5-2.7 around a step are
+ * oracle_evolve_step (both at the end of the file).
  */
 #include <math.h>
 #include <stdint.h>
@@ -609,4 +611,99 @@ ORACLE_EXPORT int oracle_ring_step(int H, int W, int C, int NK, const int* src, 
     if (U_out) memcpy(U_out, U, sizeof(double) * NK * N);
     free(num); free(cnt); free(Pd); free(ringsum); free(U); free(n_r);
     return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * The random and environmental operators of Algorithm 2 around one step:
+ * walls (Section 2.7), mutation (Section 2.5) and the penalization of
+ * exploding patterns (Section 2.6), for the shell form with localized genes
+ * that are updated.  The random draws of the iteration are inputs.
+ *   1. walls: A and P are set to 0 on the wall cells (of the input state);
+ *   2. the step of oracle_step (diffusion, potentials, alpha, mask, growth);
+ *   3. organic matter = Delta_sum(U): the cells where the sum over kernels of
+ *      the potentials exceeds eps; E_oxy = the cells with a non-organic cell
+ *      within the disk |d| <= r_oxy; E_pen = the cells with a cell outside
+ *      E_oxy within that disk (the oxygenated area, then the area around what
+ *      it does not reach);
+ *   4. mutation: P[mut_p][mut_k] += gamma_mut * mut_delta on the square of
+ *      side 2s (rows y0 - s .. y0 + s - 1, columns likewise, on the torus)
+ *      where alpha = 1;
+ *   5. penalization: P[pen_p][pen_k] += gamma_pen * pen_delta where E_pen and
+ *      alpha hold.
+ * Readings: the disk K_oxy is |d| <= r_oxy; the two convolutions of the
+ * paper are read as set operations (any cell of the disk); no clip after the
+ * two additions (the next diffusion clips).  A, P are updated in place.
+ * flags_out[H][W]: bit 0 alpha, bit 1 organic; epen_out[H][W]: E_pen;
+ * amb_out as oracle_step, plus bit 2 where the organic sum is within tau of
+ * eps.  Returns 0, or -1 on allocation failure.
+ * ------------------------------------------------------------------------- */
+static void disk_any(int H, int W, int r, const uint8_t* in, uint8_t want, uint8_t* out)
+{
+    #pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            uint8_t hit = 0;
+            for (int dy = -r; dy <= r && !hit; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    if (dy * dy + dx * dx > r * r) continue;
+                    if (in[wrap(y + dy, H) * W + wrap(x + dx, W)] == want) { hit = 1; break; }
+                }
+            out[y * W + x] = hit;
+        }
+}
+
+ORACLE_EXPORT int oracle_evolve_step(int H, int W, int C, int NK, const int* src, const int* dst,
+                                     int R, const double* K, double dt, double eps, int r_diff,
+                                     double tau, const uint8_t* walls, double gamma_mut,
+                                     int mut_half, double gamma_pen, int r_oxy, int mut_p,
+                                     int mut_k, double mut_delta, int mut_y0, int mut_x0,
+                                     int pen_p, int pen_k, double pen_delta, double* A, double* P,
+                                     uint8_t* flags_out, uint8_t* epen_out, uint8_t* amb_out)
+{
+    const long N = (long)H * W;
+    const int NP = 3 * NK;
+    if (walls)
+        for (long c = 0; c < N; ++c)
+            if (walls[c]) {
+                for (int ch = 0; ch < C; ++ch) A[(long)ch * N + c] = 0.0;
+                for (int pk = 0; pk < NP; ++pk) P[(long)pk * N + c] = 0.0;
+            }
+    double* A1 = (double*)malloc(sizeof(double) * C * N);
+    double* P1 = (double*)malloc(sizeof(double) * NP * N);
+    double* U = (double*)malloc(sizeof(double) * NK * N);
+    uint8_t* alpha = (uint8_t*)malloc(N);
+    uint8_t* organic = (uint8_t*)malloc(N);
+    uint8_t* eoxy = (uint8_t*)malloc(N);
+    uint8_t* epen = (uint8_t*)malloc(N);
+    int rc = (A1 && P1 && U && alpha && organic && eoxy && epen) ? 0 : -1;
+    if (rc == 0)
+        rc = oracle_step(H, W, C, NK, src, dst, R, K, dt, 1, NULL, NULL, NULL, 1, eps, r_diff, tau,
+                         A, P, A1, P1, U, alpha, amb_out);
+    if (rc == 0) {
+        for (long c = 0; c < N; ++c) {
+            double su = 0.0;
+            for (int k = 0; k < NK; ++k) su += U[(long)k * N + c];
+            organic[c] = (su > eps) ? 1 : 0;
+            if (amb_out && fabs(su - eps) <= tau) amb_out[c] |= 4;
+        }
+        disk_any(H, W, r_oxy, organic, 0, eoxy);   /* oxygenated: empty space in reach */
+        disk_any(H, W, r_oxy, eoxy, 0, epen);      /* around what oxygen does not reach */
+        if (gamma_mut != 0.0)
+            for (int i = 0; i < 2 * mut_half; ++i)
+                for (int j = 0; j < 2 * mut_half; ++j) {
+                    long c = wrap(mut_y0 - mut_half + i, H) * W + wrap(mut_x0 - mut_half + j, W);
+                    if (alpha[c]) P1[(long)(mut_p * NK + mut_k) * N + c] += gamma_mut * mut_delta;
+                }
+        if (gamma_pen != 0.0)
+            for (long c = 0; c < N; ++c)
+                if (epen[c] && alpha[c]) P1[(long)(pen_p * NK + pen_k) * N + c] += gamma_pen * pen_delta;
+        memcpy(A, A1, sizeof(double) * C * N);
+        memcpy(P, P1, sizeof(double) * NP * N);
+        for (long c = 0; c < N; ++c) {
+            if (flags_out) flags_out[c] = (uint8_t)(alpha[c] | (organic[c] << 1));
+            if (epen_out) epen_out[c] = epen[c];
+        }
+    }
+    free(A1); free(P1); free(U); free(alpha); free(organic); free(eoxy); free(epen);
+    return rc;
 }

@@ -55,6 +55,12 @@ def lib():
         L.oracle_ring_of.argtypes = [C.c_int] * 4
         L.oracle_ring_sizes.restype = None
         L.oracle_ring_sizes.argtypes = [C.c_int, C.c_int, dp]
+        L.oracle_evolve_step.restype = C.c_int
+        L.oracle_evolve_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, C.c_int, dp,
+                                         C.c_double, C.c_double, C.c_int, C.c_double, up,
+                                         C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
+                                         C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_double, dp, dp, up, up, up]
         L.oracle_ring_step.restype = C.c_int
         L.oracle_ring_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, C.c_int, C.c_int,
                                        C.c_double, C.c_double, C.c_int, C.c_double, dp, dp, dp, dp,
@@ -213,6 +219,35 @@ def ring_step(d: Desc, A, P):
     if rc != 0:
         raise MemoryError("oracle_ring_step failed")
     return dict(A=A1, P=P1, U=U, alpha=alpha, amb=amb)
+
+
+def evolve_step(d: Desc, A, P, walls=None, gamma_mut=0.0, mut_half=8, gamma_pen=0.0, r_oxy=6,
+                event=None):
+    """One iteration of Algorithm 2 with its operators (Sections 2.5-2.7) around
+    the shell-form step: walls on the input, the step, the penalizing area,
+    mutation, penalization.  `event` holds the iteration's random draws:
+    mut_p, mut_k, mut_delta, mut_y0, mut_x0, pen_p, pen_k, pen_delta.
+    Returns dict(A, P, flags, epen, amb) (flags: bit 0 alpha, bit 1 organic)."""
+    ev = dict(mut_p=0, mut_k=0, mut_delta=0.0, mut_y0=0, mut_x0=0, pen_p=0, pen_k=0,
+              pen_delta=0.0)
+    if event:
+        ev.update(event)
+    A = _d(A).reshape(d.C, d.H, d.W).copy()
+    P = _d(P).reshape(3, d.NK, d.H, d.W).copy()
+    w = None if walls is None else np.ascontiguousarray(walls, np.uint8)
+    flags = np.empty((d.H, d.W), np.uint8)
+    epen = np.empty((d.H, d.W), np.uint8)
+    amb = np.empty((d.H, d.W), np.uint8)
+    rc = lib().oracle_evolve_step(d.H, d.W, d.C, d.NK, _p(d.src, C.c_int), _p(d.dst, C.c_int), d.R,
+                                  _p(d.K), d.dt, d.eps, d.r_diff, d.tau, _p(w, C.c_uint8),
+                                  float(gamma_mut), int(mut_half), float(gamma_pen), int(r_oxy),
+                                  int(ev["mut_p"]), int(ev["mut_k"]), float(ev["mut_delta"]),
+                                  int(ev["mut_y0"]), int(ev["mut_x0"]), int(ev["pen_p"]),
+                                  int(ev["pen_k"]), float(ev["pen_delta"]), _p(A), _p(P),
+                                  _p(flags, C.c_uint8), _p(epen, C.c_uint8), _p(amb, C.c_uint8))
+    if rc != 0:
+        raise MemoryError("oracle_evolve_step failed")
+    return dict(A=A, P=P, flags=flags, epen=epen, amb=amb)
 
 
 def ring_rollout(d: Desc, A, P, steps: int):
