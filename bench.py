@@ -8,7 +8,8 @@ the timed region.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 
-Secondary legs in the same line: the split DFT forms on MFMA, the adjoint's
+Secondary legs in the same line: Algorithm 2's operators (walls, mutation,
+penalization) around the step, the split DFT forms on MFMA, the adjoint's
 backward/forward time ratio, the ring-decomposed kernel form (and, with
 --batched, the 256-world batched workload).
 """
@@ -221,6 +222,54 @@ def ring_form(steps: int = 20, warmup: int = 10):
                          "traffic": measured_traffic(cells, RING_TRAFFIC_FILE, STEP_SRCS)}}
 
 
+# the step's 384 B/cell plus the wall mask read (1), the flags written and read
+# twice (3) and the two area masks written and read (4)
+EVOLVE_BYTES_PER_CELL = 392
+
+
+def evolve_form(world, steps: int = 20, warmup: int = 5, r_oxy: int = 6):
+    """Algorithm 2's operators around each step of the same world: walls every
+    512 rows and columns, mutation (rate 1, squares of side 16) and the
+    penalization of exploding patterns (rate 0.2, oxygen radius r_oxy), with
+    seeded random draws per step."""
+    import numpy as np
+    import torch
+    from paper_2304_05639_amd import lenia
+    H, W = world.H, world.W
+    plan = lenia.Plan(world)
+    walls = np.zeros((H, W), np.uint8)
+    walls[::512, :] = 1
+    walls[:, ::512] = 1
+    wt = torch.tensor(walls, device="cuda")
+    rng = np.random.default_rng(2304056390 + 7)
+    events = []
+    for _ in range(warmup + steps):
+        p = int(rng.integers(2))
+        events.append(dict(mut_p=int(rng.integers(3)), mut_k=int(rng.integers(15)),
+                           mut_delta=float(rng.uniform(-0.01, 0.01)), mut_y0=int(rng.integers(H)),
+                           mut_x0=int(rng.integers(W)), pen_p=p, pen_k=int(rng.integers(15)),
+                           pen_delta=float((1 if p == 0 else -1) * rng.uniform(0, 0.01))))
+    kw = dict(walls=wt, gamma_mut=1.0, mut_half=8, gamma_pen=0.2, r_oxy=r_oxy)
+    A = torch.tensor(world.A, device="cuda")
+    P = torch.tensor(world.P, device="cuda")
+    A2, P2 = torch.empty_like(A), torch.empty_like(P)
+    plan.step_evolve(A, P, A2, P2, n_steps=warmup, events=events[:warmup], **kw)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.step_evolve(A2, P2, A, P, n_steps=steps, events=events[warmup:], **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    achieved = EVOLVE_BYTES_PER_CELL * H * W / (ms / 1e3) / 1e9
+    return {"value": H * W / (ms / 1e3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "steps": steps, "warmup": warmup,
+            "workload": f"the 4096^2 workload with walls every 512 cells, mutation (rate 1, side 16) "
+                        f"and penalization (rate 0.2, r_oxy {r_oxy}) each step",
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,9 +282,11 @@ def main():
                          "split-bf16 DFT-as-GEMM form on MFMA")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--no-dft", action="store_true", help="skip the MFMA DFT-form leg")
+    ap.add_argument("--no-evolve", action="store_true",
+                    help="skip the leg with walls, mutation and penalization")
     ap.add_argument("--no-ring", action="store_true",
                     help="skip the ring-decomposed kernel leg (slow input generation)")
-    ap.add_argument("--only", choices=["ratio", "batched", "dft", "ring"], default=None,
+    ap.add_argument("--only", choices=["ratio", "batched", "dft", "ring", "evolve"], default=None,
                     help="run a single secondary leg (for profiling) and print its JSON")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB fill, copy and sum (reference kernels for the "
@@ -273,6 +324,9 @@ def main():
         print(json.dumps({"ring_form": ring_form()}), flush=True)
         return
     world = inputs.config3()
+    if args.only == "evolve":
+        print(json.dumps({"evolve": evolve_form(world)}), flush=True)
+        return
     if args.only == "dft":
         print(json.dumps({"dft_split_bf16": dft_form(world),
                           "dft_split_f16": dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)}), flush=True)
@@ -330,6 +384,8 @@ def main():
                      "traffic": traffic},
     }
     del A2, P2, A, P
+    if not args.no_evolve and args.conv == "direct":
+        out["evolve"] = evolve_form(world)
     if not args.no_dft and args.conv == "direct":
         out["dft_split_bf16"] = dft_form(world)
         out["dft_split_f16"] = dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)

@@ -196,6 +196,51 @@ LENIA_API lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const fl
                             const void* saved, const float* gA_next, const float* gP_next,
                             float* gA_t, float* gP_t, float* gbeta, void* stream);
 
+/*
+ * The environmental and random operators of Algorithm 2 around each step of
+ * a single-world plan with localized, updated genes (shell form):
+ *   1. walls (Section 2.7): A and P are set to 0 on the wall cells of the
+ *      state the step starts from;
+ *   2. the step of lenia_step;
+ *   3. the penalizing area (Section 2.6): organic matter = the cells where
+ *      sum_k u_k > eps; E_oxy = the cells with a non-organic cell within the
+ *      disk |d| <= r_oxy; E_pen = the cells with a cell outside E_oxy within
+ *      that disk (both convolutions read as "any cell of the disk");
+ *   4. mutation (Section 2.5): gene plane (mut_p, mut_k) += gamma_mut *
+ *      mut_delta on the square of side 2 mut_half, rows mut_y0 - mut_half ..
+ *      mut_y0 + mut_half - 1 and columns likewise (wrapped), where alpha = 1;
+ *   5. penalization (Section 2.6): gene plane (pen_p, pen_k) += gamma_pen *
+ *      pen_delta where E_pen and alpha hold.
+ * No clip follows 4 and 5 (the next step's diffusion clips).  The random
+ * draws of each iteration are the caller's: one lenia_event per step.
+ */
+typedef struct {
+    const uint8_t* walls;       /* device uint8[H][W], nonzero = wall; or NULL   */
+    double gamma_mut;           /* mutation rate (the paper runs 1 and 5); 0 = off */
+    int32_t mut_half;           /* half side s of the mutated square; 2s <= H, W */
+    double gamma_pen;           /* penalization rate (the paper runs 0.2); 0 = off */
+    int32_t r_oxy;              /* oxygen disk radius, 0..16                      */
+} lenia_evolution;
+
+typedef struct {
+    int32_t mut_p, mut_k;       /* mutated gene type (0 m, 1 s, 2 h) and kernel  */
+    float mut_delta;            /* the mutation's delta                           */
+    int32_t mut_y0, mut_x0;     /* centre of the square (any int, wrapped)        */
+    int32_t pen_p, pen_k;       /* penalized gene type (0 m or 1 s) and kernel    */
+    float pen_delta;            /* the penalty's delta (its sign is the caller's) */
+} lenia_event;
+
+/*
+ * n_steps iterations of the above.  Buffers as for lenia_step (in place or
+ * out of place), except that the wall cells of (A_in, P_in) are zeroed in
+ * place first.  events: host array of n_steps entries (may be NULL when both
+ * rates are 0).  Workspace of 3 bytes per cell allocated on first use.
+ * Ring-decomposed kernels and batched plans: LENIA_ERR_UNSUPPORTED.
+ */
+LENIA_API lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_in, float* A_out,
+                                         float* P_out, int32_t n_steps, const lenia_evolution* evo,
+                                         const lenia_event* events, void* stream);
+
 LENIA_API lenia_status lenia_plan_get_info(lenia_plan_t p, lenia_plan_info* info);
 LENIA_API lenia_status lenia_plan_destroy(lenia_plan_t p);
 LENIA_API const char* lenia_status_str(lenia_status s);

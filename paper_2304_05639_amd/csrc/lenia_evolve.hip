@@ -1,0 +1,230 @@
+// The environmental and random operators of Algorithm 2 around a step on
+// gfx950: walls (Section 2.7), the penalizing area of exploding patterns
+// (Section 2.6) and the gene updates of mutation (Section 2.5) and
+// penalization (Section 2.6).  The step itself is the fused step kernel,
+// asked for a per-cell flags byte (bit 0 alpha, bit 1 organic matter
+// sum_k u_k > eps).
+#include <cmath>
+
+#include "lenia.h"
+#include "lenia_device.h"
+#include "lenia_internal.h"
+#include "lenia_plan.h"
+
+namespace lenia {
+
+constexpr int kMaxOxy = 16;
+
+// Wall cells of the state: A and all gene planes set to 0.
+__global__ __launch_bounds__(256) void walls_kernel(float* A, float* P, const uint8_t* walls,
+                                                    uint32_t HW, int C, int NPG)
+{
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= HW || !walls[idx]) return;
+    for (int c = 0; c < C; ++c) A[(size_t)c * HW + idx] = 0.f;
+    if (P)
+        for (int q = 0; q < NPG; ++q) P[(size_t)q * HW + idx] = 0.f;
+}
+
+// out(x) = 1 if some cell d of the disk |d| <= r around x (on the torus) has
+// bit `bit` of src clear.  A tile of TY x TX cells stages, for each of its
+// TY + 2r rows, the prefix counts of clear cells over its TX + 2r columns, so
+// that each disk row is one difference of two counts.
+constexpr int OXY_TY = 16, OXY_TX = 64;
+
+__global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int bit, uint8_t* out,
+                                                         int H, int W, int r)
+{
+    constexpr int MR = kMaxOxy;
+    constexpr int RY = OXY_TY + 2 * MR, RX = OXY_TX + 2 * MR + 1;
+    __shared__ uint16_t zc[RY][RX];     // zc[row][j] = clear cells among columns [0, j)
+    __shared__ int8_t half_width[MR + 1];
+    const int tiles_x = (W + OXY_TX - 1) / OXY_TX;
+    const int ty0 = (blockIdx.x / tiles_x) * OXY_TY, tx0 = (blockIdx.x % tiles_x) * OXY_TX;
+    const int ny = OXY_TY + 2 * r, nx = OXY_TX + 2 * r;
+    if (threadIdx.x <= (unsigned)r) {
+        // largest w with w^2 + dy^2 <= r^2
+        const int dy = threadIdx.x;
+        int w = 0;
+        while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
+        half_width[dy] = (int8_t)w;
+    }
+    // one thread per staged row: the prefix count over its columns
+    for (int row = threadIdx.x; row < ny; row += 256) {
+        int gy = ty0 + row - r;
+        gy = ((gy % H) + H) % H;
+        const uint8_t* srow = src + (size_t)gy * W;
+        int gx = ((tx0 - r) % W + W) % W;
+        uint16_t acc = 0;
+        zc[row][0] = 0;
+        for (int j = 0; j < nx; ++j) {
+            acc += ((srow[gx] >> bit) & 1) ? 0 : 1;
+            zc[row][j + 1] = acc;
+            gx = (gx + 1 == W) ? 0 : gx + 1;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < OXY_TY * OXY_TX; i += 256) {
+        const int ly = i / OXY_TX, lx = i % OXY_TX;
+        const int gy = ty0 + ly, gx = tx0 + lx;
+        if (gy >= H || gx >= W) continue;
+        int hit = 0;
+        for (int dy = -r; dy <= r; ++dy) {
+            const int w = half_width[dy < 0 ? -dy : dy];
+            const int row = ly + r + dy, c0 = lx + r - w, c1 = lx + r + w + 1;
+            hit |= (zc[row][c1] - zc[row][c0]) > 0;
+        }
+        out[(size_t)gy * W + gx] = (uint8_t)hit;
+    }
+}
+
+// Mutation, then penalization, of one iteration, on the new gene state.
+__global__ __launch_bounds__(256) void events_kernel(float* P, const uint8_t* flags,
+                                                     const uint8_t* epen, int H, int W, int NK,
+                                                     lenia_event ev, float mut_add, int mut_half,
+                                                     float pen_add)
+{
+    const uint32_t HW = (uint32_t)H * (uint32_t)W;
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= HW || !(flags[idx] & 1)) return;       // both act only where alpha = 1
+    const int y = (int)(idx / (uint32_t)W), x = (int)(idx - (uint32_t)y * W);
+    if (mut_add != 0.f) {
+        // offsets of (y, x) from the square's first row / column, on the torus
+        const int oy = (((y - (ev.mut_y0 - mut_half)) % H) + H) % H;
+        const int ox = (((x - (ev.mut_x0 - mut_half)) % W) + W) % W;
+        if (oy < 2 * mut_half && ox < 2 * mut_half) P[(size_t)(ev.mut_p * NK + ev.mut_k) * HW + idx] += mut_add;
+    }
+    if (pen_add != 0.f && epen[idx]) P[(size_t)(ev.pen_p * NK + ev.pen_k) * HW + idx] += pen_add;
+}
+
+}  // namespace lenia
+
+using namespace lenia;
+
+extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_in, float* A_out,
+                                          float* P_out, int32_t n_steps, const lenia_evolution* evo,
+                                          const lenia_event* events, void* stream)
+{
+    try {
+        if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
+        if (p->batched) return set_error(LENIA_ERR_UNSUPPORTED, "operators run single-world plans");
+        if (p->rings) return set_error(LENIA_ERR_UNSUPPORTED, "operators run the shell form");
+        WorldPlan& w = p->worlds[0];
+        if (w.mode != MODE_LOCAL_UPDATE)
+            return set_error(LENIA_ERR_UNSUPPORTED, "operators need localized, updated genes");
+        if (!evo) return set_error(LENIA_ERR_INVALID_ARG, "evo is NULL");
+        if (n_steps < 0) return set_error(LENIA_ERR_INVALID_ARG, "n_steps < 0");
+        if (!A_in || !A_out || !P_in || !P_out)
+            return set_error(LENIA_ERR_INVALID_ARG, "NULL state buffer");
+        if (((uintptr_t)A_in | (uintptr_t)A_out | (uintptr_t)P_in | (uintptr_t)P_out) & 3)
+            return set_error(LENIA_ERR_INVALID_ARG, "state buffers must be 4-byte aligned");
+        if ((A_in == A_out) != (P_in == P_out))
+            return set_error(LENIA_ERR_INVALID_ARG, "A and P must both be in place or both out of place");
+        if (!std::isfinite(evo->gamma_mut) || !std::isfinite(evo->gamma_pen))
+            return set_error(LENIA_ERR_INVALID_ARG, "rates must be finite");
+        if (evo->mut_half < 0 || 2 * evo->mut_half > w.H || 2 * evo->mut_half > w.W)
+            return set_error(LENIA_ERR_INVALID_ARG, "the mutated square must fit in the torus");
+        if (evo->r_oxy < 0 || evo->r_oxy > kMaxOxy)
+            return set_error(LENIA_ERR_INVALID_ARG, "r_oxy must be in [0, 16]");
+        const bool mut = (evo->gamma_mut != 0.0), pen = (evo->gamma_pen != 0.0);
+        if ((mut || pen) && n_steps > 0 && !events)
+            return set_error(LENIA_ERR_INVALID_ARG, "events are needed when a rate is nonzero");
+        for (int i = 0; i < n_steps && (mut || pen); ++i) {
+            const lenia_event& e = events[i];
+            if (mut && (e.mut_p < 0 || e.mut_p > 2 || e.mut_k < 0 || e.mut_k >= w.NK))
+                return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": mutated gene out of range");
+            if (pen && (e.pen_p < 0 || e.pen_p > 1 || e.pen_k < 0 || e.pen_k >= w.NK))
+                return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": penalized gene must be m or s");
+        }
+        hipStream_t s = (hipStream_t)stream;
+        const size_t cells = w.cells();
+        if (!p->evo_flags) {
+            void* q = nullptr;
+            if (hipMalloc(&q, 3 * cells) != hipSuccess)
+                return set_error(LENIA_ERR_OUT_OF_MEMORY, "operator workspace");
+            p->allocations.push_back(q);
+            p->ws_bytes += 3 * cells;
+            p->evo_flags = (uint8_t*)q;
+            p->evo_eoxy = p->evo_flags + cells;
+            p->evo_epen = p->evo_eoxy + cells;
+        }
+        const size_t abytes = w.a_elems() * sizeof(float), pbytes = w.p_elems() * sizeof(float);
+        const unsigned cell_blocks = (unsigned)((cells + 255) / 256);
+        const int NPG = w.gene_types * w.NK;
+        hipError_t e = hipSuccess;
+        if (n_steps == 0) {
+            if (evo->walls)
+                hipLaunchKernelGGL(walls_kernel, dim3(cell_blocks), dim3(256), 0, s, A_in, P_in, evo->walls,
+                                   (uint32_t)cells, w.C, NPG);
+            if (A_out != A_in) e = hipMemcpyAsync(A_out, A_in, abytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess && P_out != P_in) e = hipMemcpyAsync(P_out, P_in, pbytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipGetLastError();
+            return e == hipSuccess ? LENIA_OK : hip_fail(e, "operators");
+        }
+        const bool inplace = (A_in == A_out);
+        WorldArgs a = w.args_template();
+        a.tiles_x = (w.W + p->tile_x - 1) / p->tile_x;
+        a.n_tiles = ((w.H + p->tile_y - 1) / p->tile_y) * a.tiles_x;
+        a.flags_out = p->evo_flags;
+        const int oxy_tiles = ((w.H + OXY_TY - 1) / OXY_TY) * ((w.W + OXY_TX - 1) / OXY_TX);
+        float* curA = A_in;
+        float* curP = P_in;
+        for (int i = 1; i <= n_steps; ++i) {
+            float *nA, *nP;
+            if (i == n_steps && !inplace) {
+                nA = A_out;
+                nP = P_out;
+            } else if (inplace) {
+                const bool to_ws = (i % 2 == 1);
+                nA = to_ws ? w.ws_A : A_out;
+                nP = to_ws ? w.ws_P : P_out;
+            } else {
+                const bool to_ws = ((n_steps - i) % 2 == 1);
+                nA = to_ws ? w.ws_A : A_out;
+                nP = to_ws ? w.ws_P : P_out;
+            }
+            // 1. walls on the state the step starts from
+            if (evo->walls)
+                hipLaunchKernelGGL(walls_kernel, dim3(cell_blocks), dim3(256), 0, s, curA, curP, evo->walls,
+                                   (uint32_t)cells, w.C, NPG);
+            // 2. the step, with the flags
+            a.A = curA;
+            a.P = curP;
+            a.A_out = nA;
+            a.P_out = nP;
+            if (conv_is_dft(p->conv)) {
+                e = launch_dft_potentials(p, w, curA, w.dft_u, s);
+                if (e == hipSuccess) e = find_epilogue_launcher(p->table)(a, w.dft_u, w.mode, s);
+            } else {
+                e = p->step_fn(a, w.mode, s);
+            }
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+            // 3. penalizing area, 4-5. gene updates
+            if (pen) {
+                hipLaunchKernelGGL(disk_clear_kernel, dim3(oxy_tiles), dim3(256), 0, s, p->evo_flags, 1,
+                                   p->evo_eoxy, w.H, w.W, evo->r_oxy);
+                hipLaunchKernelGGL(disk_clear_kernel, dim3(oxy_tiles), dim3(256), 0, s, p->evo_eoxy, 0,
+                                   p->evo_epen, w.H, w.W, evo->r_oxy);
+            }
+            if (mut || pen) {
+                const lenia_event& ev = events[i - 1];
+                const float mut_add = mut ? (float)(evo->gamma_mut * (double)ev.mut_delta) : 0.f;
+                const float pen_add = pen ? (float)(evo->gamma_pen * (double)ev.pen_delta) : 0.f;
+                hipLaunchKernelGGL(events_kernel, dim3(cell_blocks), dim3(256), 0, s, nP, p->evo_flags,
+                                   p->evo_epen, w.H, w.W, w.NK, ev, mut_add, evo->mut_half, pen_add);
+            }
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "operator launch");
+            curA = nA;
+            curP = nP;
+        }
+        if (inplace && (n_steps % 2 == 1)) {
+            e = hipMemcpyAsync(A_out, w.ws_A, abytes, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(P_out, w.ws_P, pbytes, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "copy back");
+        }
+        return LENIA_OK;
+    } catch (...) {
+        return set_error(LENIA_ERR_STATE, "exception in lenia_step_evolve");
+    }
+}

@@ -97,6 +97,9 @@ struct WorldArgs {
     float* P_out;          // null when genes are read-only
     float* U_save;         // [NK][H][W] or null
     uint8_t* alpha_save;   // [H][W] or null
+    uint8_t* flags_out;    // [H][W] or null: bit 0 alpha, bit 1 sum_k u_k > eps (the
+                           // organic-matter mask of the penalization); disables the
+                           // tile shortcuts, which never form the potentials
     const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
     const float* wt;       // [n_orbits][C][8] the same weights by (orbit, source, slot)
     int H, W;

@@ -90,5 +90,10 @@ struct lenia_plan_ {
     hipStream_t capture_stream = nullptr;                 // private stream used for capture
     // adjoint
     lenia::BackwardWs bw;
+    // operators around the step (lenia_step_evolve): per-cell flags (alpha,
+    // organic), the oxygenated area and the penalizing area
+    uint8_t* evo_flags = nullptr;
+    uint8_t* evo_eoxy = nullptr;
+    uint8_t* evo_epen = nullptr;
     std::vector<void*> allocations;
 };

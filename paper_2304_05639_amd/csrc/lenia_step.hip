@@ -234,6 +234,12 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 #pragma unroll
         for (int q = 0; q < NP; ++q) pst(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
         if (wd.alpha_save) wd.alpha_save[ob >> 2] = alpha ? 1 : 0;
+        if (wd.flags_out) {
+            float su = 0.f;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) su += u[k];
+            wd.flags_out[ob >> 2] = (uint8_t)((alpha ? 1 : 0) | ((su > eps) ? 2 : 0));
+        }
     } else if (mode == MODE_LOCAL_READONLY) {
 #pragma unroll
         for (int k = 0; k < NK; ++k)
@@ -519,8 +525,9 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     //    1-cell ring is <= eps, no disk of the diffusion counts a value above
     //    eps, so the diffused gene is 0 on the tile (P' = 0 where alpha was 0
     //    leaves such regions behind).
-    // Decided only where the potentials are not requested.
-    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
+    // Decided only where the potentials (or the flags made from them) are not
+    // requested.
+    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr) && (wd.flags_out == nullptr);
     if (may_skip && threadIdx.x == 0) *tile_flag = 0;
     int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr;
                          // bit C: some value of gene plane 0 above eps

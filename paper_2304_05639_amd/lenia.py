@@ -22,7 +22,8 @@ FLAG_AUTOTUNE = 1
 
 API = ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan", "lenia_plan_batched",
        "lenia_step", "lenia_step_batched", "lenia_potentials", "lenia_saved_bytes", "lenia_backward",
-       "lenia_plan_get_info", "lenia_plan_destroy", "lenia_status_str", "lenia_last_error")
+       "lenia_step_evolve", "lenia_plan_get_info", "lenia_plan_destroy", "lenia_status_str",
+       "lenia_last_error")
 
 
 class LeniaError(RuntimeError):
@@ -41,6 +42,17 @@ class Desc(C.Structure):
                 ("h", C.POINTER(C.c_double)), ("eps", C.c_double), ("r_diff", C.c_int32),
                 ("conv", C.c_int32), ("tile_y", C.c_int32), ("tile_x", C.c_int32),
                 ("flags", C.c_uint32), ("n_ring", C.c_int32)]
+
+
+class Evolution(C.Structure):
+    _fields_ = [("walls", C.c_void_p), ("gamma_mut", C.c_double), ("mut_half", C.c_int32),
+                ("gamma_pen", C.c_double), ("r_oxy", C.c_int32)]
+
+
+class Event(C.Structure):
+    _fields_ = [("mut_p", C.c_int32), ("mut_k", C.c_int32), ("mut_delta", C.c_float),
+                ("mut_y0", C.c_int32), ("mut_x0", C.c_int32), ("pen_p", C.c_int32),
+                ("pen_k", C.c_int32), ("pen_delta", C.c_float)]
 
 
 class PlanInfo(C.Structure):
@@ -76,6 +88,8 @@ def lib():
         L.lenia_saved_bytes.restype = C.c_size_t
         L.lenia_backward.argtypes = [vp] + [vp] * 8 + [vp]
         L.lenia_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
+        L.lenia_step_evolve.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.POINTER(Evolution),
+                                        C.POINTER(Event), vp]
         L.lenia_plan_destroy.argtypes = [vp]
         L.lenia_status_str.argtypes = [C.c_int]
         L.lenia_status_str.restype = C.c_char_p
@@ -229,6 +243,37 @@ class Plan:
                                 _ptr(P_out) if self.update else None, int(n_steps),
                                 _ptr(saved), C.c_void_p(_stream(stream))), "lenia_step")
         return A_out, (P_out if self.update else P)
+
+    def step_evolve(self, A, P, A_out=None, P_out=None, n_steps: int = 1, walls=None,
+                    gamma_mut: float = 0.0, mut_half: int = 8, gamma_pen: float = 0.0,
+                    r_oxy: int = 6, events=None, stream=None):
+        """n_steps iterations of Algorithm 2 with walls, mutation and penalization
+        (lenia_step_evolve); the wall cells of (A, P) are zeroed in place.
+        `walls`: uint8 CUDA tensor [H, W] or None; `events`: one dict per step
+        (mut_p, mut_k, mut_delta, mut_y0, mut_x0, pen_p, pen_k, pen_delta)."""
+        import torch
+        _check_tensor(A, (self.C, self.H, self.W), "A")
+        _check_tensor(P, (self.gene_types, self.NK, self.H, self.W), "P")
+        if A_out is None:
+            A_out = torch.empty_like(A)
+        if P_out is None:
+            P_out = torch.empty_like(P)
+        _check_tensor(A_out, A.shape, "A_out")
+        _check_tensor(P_out, P.shape, "P_out")
+        if walls is not None and (walls.dtype != torch.uint8 or not walls.is_cuda or
+                                  not walls.is_contiguous() or tuple(walls.shape) != (self.H, self.W)):
+            raise ValueError("walls must be a contiguous uint8 CUDA tensor [H, W]")
+        evo = Evolution(_ptr(walls), float(gamma_mut), int(mut_half), float(gamma_pen), int(r_oxy))
+        evs = None
+        if events is not None:
+            evs = (Event * max(1, len(events)))()
+            for i, e in enumerate(events):
+                for k, v in e.items():
+                    setattr(evs[i], k, v)
+        _check(lib().lenia_step_evolve(self._h, _ptr(A), _ptr(P), _ptr(A_out), _ptr(P_out),
+                                       int(n_steps), C.byref(evo), evs, C.c_void_p(_stream(stream))),
+               "lenia_step_evolve")
+        return A_out, P_out
 
     def potentials(self, A, U=None, stream=None):
         """u_k = K~_k * A_src(k) for every kernel: tensor [NK, H, W]."""
