@@ -192,6 +192,22 @@ def dft_form(world, steps: int = 20, warmup: int = 2, conv: int = 2):
             "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile"}
 
 
+def oracle_timing(fn, n: int, budget_s: float, what: str):
+    """The FP64 oracle as it stands on a bounded sample: calls fn() (one step of
+    an n x n crop) until the time budget is spent."""
+    from oracle import oracle as O
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        fn()
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": O.threads(),
+            "kind": "oracle", "sample": f"{steps} step(s) of a {n}x{n} crop of {what}, {dt:.1f} s"}
+
+
 def ring_form(steps: int = 20, warmup: int = 10):
     """The 4096^2 workload with ring-decomposed kernels (24 rings, localized
     kernel genes): full-step throughput against the HBM floor of its
@@ -213,7 +229,16 @@ def ring_form(steps: int = 20, warmup: int = 10):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     achieved = RING_BYTES_PER_CELL * cells / (ms / 1e3) / 1e9
+    import numpy as np
+    from oracle import oracle as O
+    n = 256
+    Ac = np.ascontiguousarray(world.A[:, :n, :n])
+    Pc = np.ascontiguousarray(world.P[:, :, :n, :n])
+    dc = O.Desc(n, n, 3, 15, world.src, world.dst, world.R, world.n_shells, world.beta, world.dt,
+                1, 1, n_ring=world.n_ring)
+    cpu = oracle_timing(lambda: O.ring_step(dc, Ac, Pc), n, 4.0, "the ring-form workload")
     return {"value": cells / (ms / 1e3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "cpu_baseline": cpu,
             "steps": steps, "warmup": warmup,
             "workload": "lenia-ring-3ch15k-4096x4096: 24 rings of the R = 12 disk, 9 gene types "
                         "per kernel, 2000 blobs with their own genes",
@@ -262,7 +287,17 @@ def evolve_form(world, steps: int = 20, warmup: int = 5, r_oxy: int = 6):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     achieved = EVOLVE_BYTES_PER_CELL * H * W / (ms / 1e3) / 1e9
+    from oracle import oracle as O
+    n = 512
+    Ac = np.ascontiguousarray(world.A[:, :n, :n])
+    Pc = np.ascontiguousarray(world.P[:, :, :n, :n])
+    dc = O.Desc(n, n, 3, 15, world.src, world.dst, world.R, world.n_shells, world.beta, world.dt, 1, 1)
+    ev0 = dict(events[0], mut_y0=events[0]["mut_y0"] % n, mut_x0=events[0]["mut_x0"] % n)
+    cpu = oracle_timing(lambda: O.evolve_step(dc, Ac, Pc, walls=walls[:n, :n], gamma_mut=1.0, mut_half=8,
+                                              gamma_pen=0.2, r_oxy=r_oxy, event=ev0),
+                        n, 4.0, "the operators workload")
     return {"value": H * W / (ms / 1e3), "unit": "cell-updates/s", "ms_per_step": ms,
+            "cpu_baseline": cpu,
             "steps": steps, "warmup": warmup,
             "workload": f"the 4096^2 workload with walls every 512 cells, mutation (rate 1, side 16) "
                         f"and penalization (rate 0.2, r_oxy {r_oxy}) each step",

@@ -15,15 +15,21 @@ namespace lenia {
 
 constexpr int kMaxOxy = 16;
 
-// Wall cells of the state: A and all gene planes set to 0.
+// Wall cells of the state: A and all gene planes set to 0.  Each lane takes
+// kWallCells cells a grid apart, so that consecutive lanes read consecutive
+// mask bytes and write consecutive cells of every plane.
+constexpr int kWallCells = 4;
+
 __global__ __launch_bounds__(256) void walls_kernel(float* A, float* P, const uint8_t* walls,
                                                     uint32_t HW, int C, int NPG)
 {
-    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    if (idx >= HW || !walls[idx]) return;
-    for (int c = 0; c < C; ++c) A[(size_t)c * HW + idx] = 0.f;
-    if (P)
-        for (int q = 0; q < NPG; ++q) P[(size_t)q * HW + idx] = 0.f;
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t idx = blockIdx.x * 256u + threadIdx.x; idx < HW; idx += stride) {
+        if (!walls[idx]) continue;
+        for (int c = 0; c < C; ++c) A[(size_t)c * HW + idx] = 0.f;
+        if (P)
+            for (int q = 0; q < NPG; ++q) P[(size_t)q * HW + idx] = 0.f;
+    }
 }
 
 // out(x) = 1 if some cell d of the disk |d| <= r around x (on the torus) has
@@ -37,6 +43,7 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
 {
     constexpr int MR = kMaxOxy;
     constexpr int RY = OXY_TY + 2 * MR, RX = OXY_TX + 2 * MR + 1;
+    __shared__ uint8_t clear[RY][RX];   // 1 where the staged cell's bit is clear
     __shared__ uint16_t zc[RY][RX];     // zc[row][j] = clear cells among columns [0, j)
     __shared__ int8_t half_width[MR + 1];
     const int tiles_x = (W + OXY_TX - 1) / OXY_TX;
@@ -49,18 +56,23 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
         while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
         half_width[dy] = (int8_t)w;
     }
+    // stage the tile and its r-cell halo (wrapped), all threads, row by row; a
+    // single wrap suffices unless the torus is smaller than tile + halo
+    const bool single_wrap = (H >= ny) && (W >= nx);
+    for (int i = threadIdx.x; i < ny * nx; i += 256) {
+        const int row = i / nx, col = i - row * nx;
+        int gy = ty0 + row - r, gx = tx0 + col - r;
+        wrap2(gy, gx, H, W, single_wrap);
+        clear[row][col] = ((src[(size_t)gy * W + gx] >> bit) & 1) ? 0 : 1;
+    }
+    __syncthreads();
     // one thread per staged row: the prefix count over its columns
     for (int row = threadIdx.x; row < ny; row += 256) {
-        int gy = ty0 + row - r;
-        gy = ((gy % H) + H) % H;
-        const uint8_t* srow = src + (size_t)gy * W;
-        int gx = ((tx0 - r) % W + W) % W;
         uint16_t acc = 0;
         zc[row][0] = 0;
         for (int j = 0; j < nx; ++j) {
-            acc += ((srow[gx] >> bit) & 1) ? 0 : 1;
+            acc += clear[row][j];
             zc[row][j + 1] = acc;
-            gx = (gx + 1 == W) ? 0 : gx + 1;
         }
     }
     __syncthreads();
@@ -150,11 +162,12 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
         }
         const size_t abytes = w.a_elems() * sizeof(float), pbytes = w.p_elems() * sizeof(float);
         const unsigned cell_blocks = (unsigned)((cells + 255) / 256);
+        const unsigned wall_blocks = (unsigned)((cells + kWallCells * 256 - 1) / (kWallCells * 256));
         const int NPG = w.gene_types * w.NK;
         hipError_t e = hipSuccess;
         if (n_steps == 0) {
             if (evo->walls)
-                hipLaunchKernelGGL(walls_kernel, dim3(cell_blocks), dim3(256), 0, s, A_in, P_in, evo->walls,
+                hipLaunchKernelGGL(walls_kernel, dim3(wall_blocks), dim3(256), 0, s, A_in, P_in, evo->walls,
                                    (uint32_t)cells, w.C, NPG);
             if (A_out != A_in) e = hipMemcpyAsync(A_out, A_in, abytes, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess && P_out != P_in) e = hipMemcpyAsync(P_out, P_in, pbytes, hipMemcpyDeviceToDevice, s);
@@ -185,7 +198,7 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
             }
             // 1. walls on the state the step starts from
             if (evo->walls)
-                hipLaunchKernelGGL(walls_kernel, dim3(cell_blocks), dim3(256), 0, s, curA, curP, evo->walls,
+                hipLaunchKernelGGL(walls_kernel, dim3(wall_blocks), dim3(256), 0, s, curA, curP, evo->walls,
                                    (uint32_t)cells, w.C, NPG);
             // 2. the step, with the flags
             a.A = curA;

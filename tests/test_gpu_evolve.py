@@ -182,3 +182,25 @@ def test_evolve_full_size_sampled_windows(L, oracle):
         rr = dict(A=r["A"][(slice(None),) + inner], P=r["P"][(slice(None), slice(None)) + inner],
                   amb=r["amb"][inner])
         _compare(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw), r_oxy, TOL_STATE)
+
+
+def test_evolve_multi_step_call_matches_single_steps(L):
+    """n iterations in one call (ping-pong buffers, in place and out of place)
+    equal one call per iteration with the same events, bitwise."""
+    import torch
+    H, W = 72, 96
+    w = inputs.test_world(H, W, seed=807, n_blobs=14)
+    plan = L.Plan(w)
+    walls = torch.tensor(_walls(H, W), device="cuda")
+    evs = _events(np.random.default_rng(807), 3, H, W)
+    kw = dict(walls=walls, gamma_mut=5.0, mut_half=6, gamma_pen=0.2, r_oxy=3)
+    A, P = dev(w.A), dev(w.P)
+    B, Q = A.clone(), P.clone()
+    for t in range(3):
+        B, Q = plan.step_evolve(B, Q, events=[evs[t]], **kw)
+    A3, P3 = plan.step_evolve(A.clone(), P.clone(), n_steps=3, events=evs, **kw)
+    Ai, Pi = A.clone(), P.clone()
+    plan.step_evolve(Ai, Pi, Ai, Pi, n_steps=3, events=evs, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(A3, B) and torch.equal(P3, Q)
+    assert torch.equal(Ai, B) and torch.equal(Pi, Q)
