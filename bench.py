@@ -79,10 +79,26 @@ def cpu_baseline(world, budget_s: float = 12.0):
         if time.perf_counter() - t0 >= budget_s or steps >= 8:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on a 256 x 256 crop
+    m = 256
+    A1 = np.ascontiguousarray(world.A[:, :m, :m])
+    P1 = np.ascontiguousarray(world.P[:, :, :m, :m])
+    d1 = O.Desc(m, m, 3, 15, world.src, world.dst, world.R, world.n_shells, world.beta,
+                world.dt, 1, 1)
+    O.set_threads(1)
+    s1 = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < 3.0:
+        O.step(d1, A1, P1)
+        s1 += 1
+    dt1 = time.perf_counter() - t1
+    O.set_threads(O.threads())
     return {"value": n * n * steps / dt, "unit": "cell-updates/s", "cores": O.threads(),
             "kind": "oracle",
             "sample": f"{steps} step(s) of a {n}x{n} crop of the 4096^2 workload (FP64 direct "
-                      f"convolution, OpenMP over rows), {dt:.1f} s"}
+                      f"convolution, OpenMP over rows), {dt:.1f} s",
+            "value_1_thread": m * m * s1 / dt1,
+            "sample_1_thread": f"{s1} step(s) of a {m}x{m} crop on one thread, {dt1:.1f} s"}
 
 
 def backward_forward_ratio(steps_T: int = 64, ckpt: int = 8, reps: int = 3, conv: int = 1):
@@ -208,6 +224,33 @@ def oracle_timing(fn, n: int, budget_s: float, what: str):
             "kind": "oracle", "sample": f"{steps} step(s) of a {n}x{n} crop of {what}, {dt:.1f} s"}
 
 
+def small_worlds():
+    """The 64^2 single-channel world (global genes, one R = 13 kernel) timed as
+    latency over 100 steps in one call, and the 512^2 three-channel world as
+    throughput over 100 steps (its working set stays in the 256 MB
+    Infinity Cache)."""
+    import torch
+    from paper_2304_05639_amd import inputs, lenia
+    out = {}
+    for name, w, n in (("c1_64x64_global", inputs.config1(), 100), ("c2_512x512", inputs.config2(), 100)):
+        plan = lenia.Plan(w)
+        A = torch.tensor(w.A, device="cuda")
+        P = torch.tensor(w.P, device="cuda") if w.P is not None else None
+        A2 = torch.empty_like(A)
+        P2 = torch.empty_like(P) if P is not None else None
+        plan.step(A, P, A2, P2, n_steps=10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        plan.step(A2, P2, A, P, n_steps=n)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        out[name] = {"us_per_step": ms * 1e3, "steps_per_s": 1e3 / ms,
+                     "cell_updates_per_s": w.H * w.W / (ms / 1e3), "steps": n}
+    return out
+
+
 def ring_form(steps: int = 20, warmup: int = 10):
     """The 4096^2 workload with ring-decomposed kernels (24 rings, localized
     kernel genes): full-step throughput against the HBM floor of its
@@ -321,7 +364,8 @@ def main():
                     help="skip the leg with walls, mutation and penalization")
     ap.add_argument("--no-ring", action="store_true",
                     help="skip the ring-decomposed kernel leg (slow input generation)")
-    ap.add_argument("--only", choices=["ratio", "batched", "dft", "ring", "evolve"], default=None,
+    ap.add_argument("--only", choices=["ratio", "batched", "dft", "ring", "evolve", "small"],
+                    default=None,
                     help="run a single secondary leg (for profiling) and print its JSON")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a 1 GiB fill, copy and sum (reference kernels for the "
@@ -354,6 +398,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched": batched_throughput()}), flush=True)
+        return
+    if args.only == "small":
+        print(json.dumps({"small_worlds": small_worlds()}), flush=True)
         return
     if args.only == "ring":
         print(json.dumps({"ring_form": ring_form()}), flush=True)
@@ -421,6 +468,8 @@ def main():
     del A2, P2, A, P
     if not args.no_evolve and args.conv == "direct":
         out["evolve"] = evolve_form(world)
+    if args.conv == "direct":
+        out["small_worlds"] = small_worlds()
     if not args.no_dft and args.conv == "direct":
         out["dft_split_bf16"] = dft_form(world)
         out["dft_split_f16"] = dft_form(world, conv=lenia.CONV_DFT_SPLIT_F16)

@@ -39,6 +39,20 @@
 
 #define ORACLE_EXPORT __attribute__((visibility("default")))
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops (for timing the oracle on one core or all). */
+ORACLE_EXPORT void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static double core_fn(double r)
 {
     if (r <= 0.0 || r >= 1.0) return 0.0;

@@ -51,6 +51,8 @@ def lib():
         L.oracle_step_vjp.argtypes = common + [dp, dp, dp, dp, dp, dp, dp, dp, up]
         L.oracle_beta_grad.restype = C.c_int
         L.oracle_beta_grad.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.oracle_set_threads.restype = None
+        L.oracle_set_threads.argtypes = [C.c_int]
         L.oracle_ring_of.restype = C.c_int
         L.oracle_ring_of.argtypes = [C.c_int] * 4
         L.oracle_ring_sizes.restype = None
@@ -257,6 +259,11 @@ def ring_rollout(d: Desc, A, P, steps: int):
         r = ring_step(d, A, P)
         A, P = r["A"], r["P"]
     return A, P
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (0 leaves them)."""
+    lib().oracle_set_threads(int(n))
 
 
 def threads() -> int:
