@@ -109,6 +109,19 @@ def test_null_descriptor_rejected():
     assert L.lib().lenia_desc_validate(None) == L.ERR_INVALID_ARG
 
 
+def test_null_plan_rejected_by_every_entry_point():
+    # validated on the host before anything touches a device
+    import ctypes
+    lib = L.lib()
+    evo = L.Evolution(None, 0.0, 0, 0.0, 0)
+    assert lib.lenia_step(None, None, None, None, None, 1, None, None) == L.ERR_INVALID_ARG
+    assert lib.lenia_step_evolve(None, None, None, None, None, 1, ctypes.byref(evo), None,
+                                 None) == L.ERR_INVALID_ARG
+    assert lib.lenia_potentials(None, None, None, None) == L.ERR_INVALID_ARG
+    assert lib.lenia_backward(None, *([None] * 9)) == L.ERR_INVALID_ARG
+    assert lib.lenia_saved_bytes(None) == 0
+
+
 @pytest.mark.parametrize("seed", [3, 4])
 def test_plan_kernels_match_oracle(oracle, seed):
     w = inputs.test_world(32, 32, seed=seed, n_blobs=1)
