@@ -111,6 +111,8 @@ struct WorldArgs {
     float cnt_bias;        // -cnt_scale * eps (exact)
     float skip_thr;        // eps * (1 - 2^-10), rounded down: a tile whose window of one
                            // source channel stays <= skip_thr has alpha = 0 everywhere
+    float org_thr;         // skip_thr / NK, rounded down: a tile whose window stays
+                           // <= org_thr in every channel has sum_k u_k < eps everywhere
     float gm[kMaxK], gs[kMaxK], gh[kMaxK];   // global genes (MODE_GLOBAL)
 };
 

@@ -40,6 +40,10 @@ WorldArgs WorldPlan::args_template() const
         float f = (float)t;
         if ((double)f > t) f = std::nextafter(f, -1.0f);
         a.skip_thr = f;
+        const double to = (double)f / (double)(NK > 0 ? NK : 1);
+        float g = (float)to;
+        if ((double)g > to) g = std::nextafter(g, -1.0f);
+        a.org_thr = g;
     }
     for (int k = 0; k < NK && k < kMaxK; ++k) {
         if (!gm.empty()) {

@@ -262,7 +262,9 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 }
 
 // Outputs of the thread's Q vertically adjacent cells (gy + q, gx) whose alpha
-// is 0 (no growth, genes masked to 0): A' = clip01(A), P' = 0.  c points at the
+// is 0 (no growth, genes masked to 0): A' = clip01(A), P' = 0, and flags 0
+// when requested (only tiles whose potentials all stay below eps / NK skip
+// then).  c points at the
 // first cell in the staged tile (channel 0); cells past the torus edge are
 // skipped.  Planes are the outer loop, so each plane's descriptor is used for
 // all the cells and then dropped.
@@ -296,6 +298,11 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             if (in[q]) wd.alpha_save[ob[q] >> 2] = 0;
+    }
+    if (wd.flags_out) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (in[q]) wd.flags_out[ob[q] >> 2] = 0;
     }
 }
 
@@ -525,12 +532,16 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     //    1-cell ring is <= eps, no disk of the diffusion counts a value above
     //    eps, so the diffused gene is 0 on the tile (P' = 0 where alpha was 0
     //    leaves such regions behind).
-    // Decided only where the potentials (or the flags made from them) are not
-    // requested.
-    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr) && (wd.flags_out == nullptr);
+    // Decided only where the potentials are not requested.  Where the flags
+    // (alpha, organic sum_k u_k > eps) are, only a tile whose window stays at
+    // or below org_thr = skip_thr / NK in every channel is skipped: there every
+    // u_k is at most org_thr, so the sum is below eps and both flags are 0.
+    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
+    const bool want_flags = (wd.flags_out != nullptr);
     if (may_skip && threadIdx.x == 0) *tile_flag = 0;
-    int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr;
-                         // bit C: some value of gene plane 0 above eps
+    int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr
+                         // (above org_thr with flags); bit C: some value of gene
+                         // plane 0 above eps (without flags)
 
     // a single wrap suffices unless the torus is smaller than tile + halo
     const bool single_wrap = (H >= TY + R) && (W >= TX + R);
@@ -577,14 +588,17 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             }
         }
         if (may_skip) {
+            const float thr = want_flags ? wd.org_thr : wd.skip_thr;
 #pragma unroll
             for (int ch = 0; ch < T::C; ++ch) {
                 bool above = false;
 #pragma unroll
                 for (int it = 0; it < IT; ++it)
-                    above = above || ((threadIdx.x + it * NT < NG) && (v[it][ch] > wd.skip_thr));
+                    above = above || ((threadIdx.x + it * NT < NG) && (v[it][ch] > thr));
                 wave_bits |= (__ballot(above) != 0ull) ? (1 << ch) : 0;
             }
+        }
+        if (may_skip && !want_flags) {
             // gene plane 0 on the tile plus a 1-cell ring
             constexpr int G1X = TX + 2, NG1 = (TY + 2) * G1X;
             const plane_t p0 = plane(wd.P, 4u * (uint32_t)HW);
@@ -606,8 +620,9 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     if (may_skip) {
         if ((threadIdx.x & 63) == 0 && wave_bits != 0) atomicOr(tile_flag, wave_bits);
         __syncthreads();
-        if (*tile_flag != (2 << T::C) - 1) {
-            // an empty channel or a dead gene plane: alpha = 0 on the tile
+        if (want_flags ? (*tile_flag == 0) : (*tile_flag != (2 << T::C) - 1)) {
+            // an empty channel or a dead gene plane (with flags: every channel
+            // empty): alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
             write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
