@@ -67,6 +67,7 @@ constexpr int YT_P = DT2 + 8;
 constexpr int XH_P = DT2 + 4;
 constexpr int ZC_P = DT2 + 8;
 constexpr int ZC_ROWS = 48;
+constexpr int UST_P = DT2 + 8;
 
 struct DftTables {
     const void* f1t;      // [2][128][64]  hi, lo of [C | -S]^T
@@ -131,20 +132,23 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     const E* f3m = (const E*)g.t.f3;
     const E* f4t = (const E*)g.t.f4t;
     constexpr int V = DT - 2 * R;
-    constexpr int NK = T::NK;
-    // LDS: the transformed channels (fp32) + a scratch region shared by the
-    // forward stages (Xs, Yt) and the inverse stages (Zc)
-    constexpr int XH_FLOATS = T::C * DT * XH_P;
-    constexpr int SCRATCH_BF16 = 2 * DT * XS_P + 2 * DT * YT_P;
-    static_assert(2 * ZC_ROWS * ZC_P <= SCRATCH_BF16, "scratch too small");
+    // LDS: the transformed channel being processed (fp32) + a scratch region
+    // shared by the forward stages (Xs, Yt) and the inverse stages (Zc, and the
+    // spectral product Ust of the current kernel, split once per workgroup)
+    constexpr int XH_FLOATS = DT * XH_P;
+    constexpr int FWD_E = 2 * DT * XS_P + 2 * DT * YT_P;
+    constexpr int INV_E = 2 * ZC_ROWS * ZC_P + 2 * DT * UST_P;
+    constexpr int SCRATCH_E = (FWD_E > INV_E) ? FWD_E : INV_E;
     __shared__ float xh[XH_FLOATS];
-    __shared__ E scr[SCRATCH_BF16];
+    __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
     E* xs_hi = scr;
     E* xs_lo = scr + DT * XS_P;
     E* yt_hi = scr + 2 * DT * XS_P;
     E* yt_lo = yt_hi + DT * YT_P;
     E* zc_hi = scr;
     E* zc_lo = scr + ZC_ROWS * ZC_P;
+    E* ust_hi = scr + 2 * ZC_ROWS * ZC_P;
+    E* ust_lo = ust_hi + DT * UST_P;
 
     const int H = g.H, W = g.W;
     const size_t HW = (size_t)H * W;
@@ -155,7 +159,36 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     const int lr = lane & 15, lk = (lane >> 4) * 8, ld = (lane >> 4) * 4;
     const bool single_wrap = (H >= DT) && (W >= DT);
 
-    // ---- forward transform of each source channel --------------------------
+    // ---- per kernel: spectral product and inverse transform -----------------
+    // GEMM3 has 4 row blocks x 5 column blocks (2V rows of Z, padded to 80):
+    // wave w computes column block w for every row block, and row block w of
+    // column block 4, five tiles each; the B fragments of its two column
+    // blocks stay in registers.
+    constexpr int NB3 = (2 * V + 15) / 16;
+    static_assert(NB3 == 5, "GEMM3 is laid out for 5 column blocks");
+    ev8 b3h[2][4], b3l[2][4];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int nt = (q == 0) ? wave : 4;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int row = 16 * nt + lr, k0 = 32 * ks + lk;
+            b3h[q][ks] = ld8(f3m + row * DT2 + k0);
+            b3l[q][ks] = ld8(f3m + 80 * DT2 + row * DT2 + k0);
+        }
+    }
+    // GEMM4: wave w < 3 handles output column block w; B fragments in registers
+    ev8 b4h[4], b4l[4];
+    {
+        const int row = 16 * (wave < 3 ? wave : 0) + lr;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            b4h[ks] = ld8(f4t + row * DT2 + 32 * ks + lk);
+            b4l[ks] = ld8(f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
+        }
+    }
+
+    // ---- per source channel: forward transform, then its kernels ------------
     for (int s = 0; s < T::C; ++s) {
         __syncthreads();
         // stage the 64 x 64 window (wrapped) as bf16 hi / lo
@@ -229,117 +262,100 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) {
                     const int f2 = 16 * n + lr, r = 16 * (2 * wave + m) + ld;
-                    *(f32x4*)(xh + (s * DT + f2) * XH_P + r) = acc[m][n];
+                    *(f32x4*)(xh + f2 * XH_P + r) = acc[m][n];
                 }
-        }
-    }
-    __syncthreads();
-
-    // ---- per kernel: spectral product and inverse transform -----------------
-    // GEMM3 column blocks (of 2V rows of Z, padded to 80) handled by this wave:
-    // 0 and 4 for wave 0, wave w otherwise; their B fragments stay in registers.
-    constexpr int NB3 = (2 * V + 15) / 16;
-    static_assert(NB3 == 5, "GEMM3 is laid out for 5 column blocks");
-    const int nb3 = (wave == 0) ? 2 : 1;
-    ev8 b3h[2][4], b3l[2][4];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int nt = (q == 0) ? wave : 4;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int row = 16 * nt + lr, k0 = 32 * ks + lk;
-            b3h[q][ks] = ld8(f3m + row * DT2 + k0);
-            b3l[q][ks] = ld8(f3m + 80 * DT2 + row * DT2 + k0);
-        }
-    }
-    // GEMM4: wave w < 3 handles output column block w; B fragments in registers
-    ev8 b4h[4], b4l[4];
-    {
-        const int row = 16 * (wave < 3 ? wave : 0) + lr;
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            b4h[ks] = ld8(f4t + row * DT2 + 32 * ks + lk);
-            b4l[ks] = ld8(f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
-        }
-    }
-
-#pragma unroll 1
-    for (int k = 0; k < NK; ++k) {
-        const int s = T::src[k];
-        const float* kh = g.t.khat + (size_t)k * DT * DT;
-        // GEMM3: Z^T (64 x 80) = Ust^T (64 x 128) F3^T; wave handles all 4 row blocks
-        f32x4 acc[2][4];
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k0 = 32 * ks + lk;          // f1 + 64 (im)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int f2 = 16 * m + lr;
-                const f32x4 x0v = *(const f32x4*)(xh + (s * DT + f2) * XH_P + k0);
-                const f32x4 x1v = *(const f32x4*)(xh + (s * DT + f2) * XH_P + k0 + 4);
-                const f32x4 k0v = *(const f32x4*)(kh + f2 * DT + (k0 % DT));
-                const f32x4 k1v = *(const f32x4*)(kh + f2 * DT + (k0 % DT) + 4);
-                float u8[8];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    u8[j] = x0v[j] * k0v[j];
-                    u8[4 + j] = x1v[j] * k1v[j];
-                }
-                ev8 ah, al;
-                split8<E>(u8, ah, al);
-                acc[0][m] = mma3<E>(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
-                if (nb3 == 2) acc[1][m] = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc[1][m]);
-            }
-        }
-        __syncthreads();    // previous kernel's GEMM4 finished reading Zc
-        // Z^T row f2 = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][64 (p' >= V) + f2]
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q == 1 && nb3 != 2) break;
-            const int nt = (q == 0) ? wave : 4;
-            const int pp = 16 * nt + lr;
-            if (pp < 2 * V) {
-                const int p = (pp < V) ? pp : pp - V, col0 = (pp < V) ? 0 : DT;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int off = p * ZC_P + col0 + 16 * m + ld;
-                    st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m]);
-                }
-            }
         }
         __syncthreads();
-        // GEMM4: u (48 x 48) = Zc (48 x 128) F4; wave w < 3 computes column block w
-        if (wave < 3) {
-            f32x4 o[3];
+#pragma unroll 1
+        for (int slot = 0; slot < T::KPS; ++slot) {
+            const int k = T::kidx[s][slot];
+            const float* kh = g.t.khat + (size_t)k * DT * DT;
+            // the spectral product U = Xh * Khat (real spectrum, both halves), split
+            // into LDS once for all waves
+            for (int i = threadIdx.x; i < DT * (DT2 / 8); i += 256) {
+                const int f2 = i / (DT2 / 8), c8 = (i % (DT2 / 8)) * 8;
+                const f32x4 x0v = *(const f32x4*)(xh + f2 * XH_P + c8);
+                const f32x4 x1v = *(const f32x4*)(xh + f2 * XH_P + c8 + 4);
+                const f32x4 k0v = *(const f32x4*)(kh + f2 * DT + (c8 % DT));
+                const f32x4 k1v = *(const f32x4*)(kh + f2 * DT + (c8 % DT) + 4);
+                float u8[8];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q < 4; ++q) {
+                    u8[q] = x0v[q] * k0v[q];
+                    u8[4 + q] = x1v[q] * k1v[q];
+                }
+                ev8 uh, ul;
+                split8<E>(u8, uh, ul);
+                *(ev8*)(ust_hi + f2 * UST_P + c8) = uh;
+                *(ev8*)(ust_lo + f2 * UST_P + c8) = ul;
+            }
+            __syncthreads();
+            // GEMM3: Z^T (64 x 80) = Ust^T (64 x 128) F3^T; wave handles all 4 row blocks
+            f32x4 acc[2][4];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                const int k0 = 32 * ks + lk;
+                const int k0 = 32 * ks + lk;          // f1 + 64 (im)
 #pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    const int row = 16 * m + lr;
-                    const ev8 ah = ld8(zc_hi + row * ZC_P + k0);
-                    const ev8 al = ld8(zc_lo + row * ZC_P + k0);
-                    o[m] = mma3<E>(ah, al, b4h[ks], b4l[ks], o[m]);
+                for (int m = 0; m < 4; ++m) {
+                    const int f2 = 16 * m + lr;
+                    const ev8 ah = ld8(ust_hi + f2 * UST_P + k0);
+                    const ev8 al = ld8(ust_lo + f2 * UST_P + k0);
+                    acc[0][m] = mma3<E>(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
+                    if (m == wave) acc[1][0] = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc[1][0]);
                 }
             }
-            // u row p = 16m + ld + j, column q = 16w + lr
-            const int qx = 16 * wave + lr;
-            const int gx = x0 + qx;
-            if (qx < V && gx < W) {
-                float* uk = g.U + (size_t)k * HW;
+            __syncthreads();    // every wave has read Ust; the previous GEMM4 is done with Zc
+            // Z^T row f2 = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][64 (p' >= V) + f2]
 #pragma unroll
-                for (int m = 0; m < 3; ++m)
+            for (int q = 0; q < 2; ++q) {
+                const int nt = (q == 0) ? wave : 4;
+                const int pp = 16 * nt + lr;
+                if (pp < 2 * V) {
+                    const int p = (pp < V) ? pp : pp - V, col0 = (pp < V) ? 0 : DT;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int p = 16 * m + ld + j, gy = y0 + p;
-                        if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j];
+                    for (int m = 0; m < 4; ++m) {
+                        if (q == 1 && m != 0) break;
+                        // column block 4 holds row block `wave` only, in acc[1][0]
+                        const int mm = (q == 0) ? m : wave;
+                        const int off = p * ZC_P + col0 + 16 * mm + ld;
+                        st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m]);
                     }
+                }
+            }
+            __syncthreads();
+            // GEMM4: u (48 x 48) = Zc (48 x 128) F4; wave w < 3 computes column block w
+            if (wave < 3) {
+                f32x4 o[3];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k0 = 32 * ks + lk;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) {
+                        const int row = 16 * m + lr;
+                        const ev8 ah = ld8(zc_hi + row * ZC_P + k0);
+                        const ev8 al = ld8(zc_lo + row * ZC_P + k0);
+                        o[m] = mma3<E>(ah, al, b4h[ks], b4l[ks], o[m]);
+                    }
+                }
+                // u row p = 16m + ld + j, column q = 16w + lr
+                const int qx = 16 * wave + lr;
+                const int gx = x0 + qx;
+                if (qx < V && gx < W) {
+                    float* uk = g.U + (size_t)k * HW;
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int p = 16 * m + ld + j, gy = y0 + p;
+                            if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j];
+                        }
+                }
             }
         }
     }
