@@ -304,17 +304,6 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
         for (int q = 0; q < Q; ++q)
             if (in[q]) wd.flags_out[ob[q] >> 2] = 0;
     }
-    if (wd.U_save) {
-        // only tiles whose window is exactly 0 skip when the potentials are
-        // requested: every u_k is exactly 0
-#pragma unroll
-        for (int k = 0; k < T::NK; ++k) {
-            const plane_t pl = plane(wd.U_save + (size_t)k * HW, pb);
-#pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (in[q]) pst(pl, ob[q], 0.f);
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -543,19 +532,16 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     //    1-cell ring is <= eps, no disk of the diffusion counts a value above
     //    eps, so the diffused gene is 0 on the tile (P' = 0 where alpha was 0
     //    leaves such regions behind).
-    // Where the flags (alpha, organic sum_k u_k > eps) are requested, only a
-    // tile whose window stays at or below org_thr = skip_thr / NK in every
-    // channel is skipped: there every u_k is at most org_thr, so the sum is
-    // below eps and both flags are 0.  Where the potentials themselves are
-    // requested, only a tile whose window is exactly 0 in every channel is
-    // skipped: there every u_k is exactly 0, and is written as such.
-    const bool may_skip = (mode == MODE_LOCAL_UPDATE);
-    const bool want_u = (wd.U_save != nullptr), want_flags = (wd.flags_out != nullptr);
-    const bool all_channels = want_u || want_flags;   // skip only tiles empty in every channel
+    // Decided only where the potentials are not requested.  Where the flags
+    // (alpha, organic sum_k u_k > eps) are, only a tile whose window stays at
+    // or below org_thr = skip_thr / NK in every channel is skipped: there every
+    // u_k is at most org_thr, so the sum is below eps and both flags are 0.
+    const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
+    const bool want_flags = (wd.flags_out != nullptr);
     if (may_skip && threadIdx.x == 0) *tile_flag = 0;
     int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr
-                         // (above org_thr with flags, nonzero with potentials);
-                         // bit C: some value of gene plane 0 above eps (neither)
+                         // (above org_thr with flags); bit C: some value of gene
+                         // plane 0 above eps (without flags)
 
     // a single wrap suffices unless the torus is smaller than tile + halo
     const bool single_wrap = (H >= TY + R) && (W >= TX + R);
@@ -608,12 +594,11 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
                 bool above = false;
 #pragma unroll
                 for (int it = 0; it < IT; ++it)
-                    above = above || ((threadIdx.x + it * NT < NG) &&
-                                      (want_u ? (v[it][ch] != 0.f) : (v[it][ch] > thr)));
+                    above = above || ((threadIdx.x + it * NT < NG) && (v[it][ch] > thr));
                 wave_bits |= (__ballot(above) != 0ull) ? (1 << ch) : 0;
             }
         }
-        if (may_skip && !all_channels) {
+        if (may_skip && !want_flags) {
             // gene plane 0 on the tile plus a 1-cell ring
             constexpr int G1X = TX + 2, NG1 = (TY + 2) * G1X;
             const plane_t p0 = plane(wd.P, 4u * (uint32_t)HW);
@@ -635,9 +620,9 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     if (may_skip) {
         if ((threadIdx.x & 63) == 0 && wave_bits != 0) atomicOr(tile_flag, wave_bits);
         __syncthreads();
-        if (all_channels ? (*tile_flag == 0) : (*tile_flag != (2 << T::C) - 1)) {
-            // an empty channel or a dead gene plane (with flags or potentials:
-            // every channel empty): alpha = 0 on the tile
+        if (want_flags ? (*tile_flag == 0) : (*tile_flag != (2 << T::C) - 1)) {
+            // an empty channel or a dead gene plane (with flags: every channel
+            // empty): alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
             write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
