@@ -225,7 +225,7 @@ typedef struct {
 typedef struct {
     int32_t mut_p, mut_k;       /* mutated gene type (0 m, 1 s, 2 h) and kernel  */
     float mut_delta;            /* the mutation's delta                           */
-    int32_t mut_y0, mut_x0;     /* centre of the square (any int, wrapped)        */
+    int32_t mut_y0, mut_x0;     /* centre of the square (|.| <= 2^30, wrapped)    */
     int32_t pen_p, pen_k;       /* penalized gene type (0 m or 1 s) and kernel    */
     float pen_delta;            /* the penalty's delta (its sign is the caller's) */
 } lenia_event;

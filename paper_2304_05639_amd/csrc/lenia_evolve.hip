@@ -5,6 +5,7 @@
 // asked for a per-cell flags byte (bit 0 alpha, bit 1 organic matter
 // sum_k u_k > eps).
 #include <cmath>
+#include <cstdlib>
 
 #include "lenia.h"
 #include "lenia_device.h"
@@ -145,6 +146,12 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
             const lenia_event& e = events[i];
             if (mut && (e.mut_p < 0 || e.mut_p > 2 || e.mut_k < 0 || e.mut_k >= w.NK))
                 return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": mutated gene out of range");
+            if (mut && (std::abs((long long)e.mut_y0) > (1ll << 30) || std::abs((long long)e.mut_x0) > (1ll << 30)))
+                return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": square centre beyond +-2^30");
+            if (mut && !std::isfinite(e.mut_delta))
+                return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": delta must be finite");
+            if (pen && !std::isfinite(e.pen_delta))
+                return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": delta must be finite");
             if (pen && (e.pen_p < 0 || e.pen_p > 1 || e.pen_k < 0 || e.pen_k >= w.NK))
                 return set_error(LENIA_ERR_INVALID_ARG, "event " + std::to_string(i) + ": penalized gene must be m or s");
         }
