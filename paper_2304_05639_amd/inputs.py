@@ -282,3 +282,47 @@ def test_world(H: int, W: int, seed: int, n_blobs: Optional[int] = None,
     nb = blobs_for_side(int(np.sqrt(H * W))) if n_blobs is None else n_blobs
     return localized_world(rng, H, W, nb, R=R, genotype_update=genotype_update,
                            dt=dt, name=f"test-{H}x{W}-s{seed}")
+
+
+# ---- worlds too large to draw on the host -----------------------------------
+
+def large_world(H: int, W: int, seed: int, n_channels: int = 3) -> World:
+    """Descriptor of a world drawn on the device by device_state (A and P are
+    None here).  3 channels: the 15-kernel table, shells drawn as in
+    localized_world from default_rng(seed); 1 channel: the global-gene kernel
+    of orbium_like_world."""
+    if n_channels == 1:
+        w = orbium_like_world(seed=seed, H=8, W=8, patch=4)
+        return dataclasses.replace(w, H=H, W=W, A=None, name=f"global-1ch-{H}x{W}")
+    rng = np.random.default_rng(seed)
+    n_shells, beta = _draw_shells(rng, 15)
+    return World(H=H, W=W, n_channels=3, n_kernels=15, src=KERNEL_SRC_3CH,
+                 dst=KERNEL_DST_3CH, R=12, n_shells=n_shells, beta=beta, dt=0.2,
+                 localized=1, genotype_update=1, m=None, s=None, h=None, eps=0.01,
+                 r_diff=1, A=None, P=None, name=f"large-3ch15k-{H}x{W}")
+
+
+def device_state(w: World, seed: int, block: int = 1024, device: str = "cuda"):
+    """(A, P) of world w drawn on the device by torch's generator seeded with
+    `seed`, in this order: A uniform in [0, 1) (all channels at once), then for
+    p in (m, s, h) and k ascending, P[p, k] uniform in GENE_RANGES[p].  The
+    block x block squares with (y // block + x // block) odd are emptied in
+    every channel, and the m gene of kernel 0 is 0 on rows [0, block), so that
+    tiles without matter and tiles with a dead gene plane both occur.  P is
+    None for global genes."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    A = torch.rand((w.n_channels, w.H, w.W), generator=g, device=device)
+    yb = (torch.arange(w.H, device=device) // block) % 2
+    xb = (torch.arange(w.W, device=device) // block) % 2
+    A.masked_fill_((yb[:, None] ^ xb[None, :]).bool(), 0.0)
+    if not w.localized:
+        return A, None
+    P = torch.empty((3, w.n_kernels, w.H, w.W), device=device)
+    for pi, p in enumerate(("m", "s", "h")):
+        lo, hi = GENE_RANGES[p]
+        for k in range(w.n_kernels):
+            P[pi, k].uniform_(lo, hi, generator=g)
+    P[0, 0, :block, :] = 0.0
+    return A, P

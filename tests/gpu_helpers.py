@@ -3,6 +3,11 @@ FP64 oracle on identical FP32 inputs)."""
 import numpy as np
 
 TOL_STATE = 1e-5      # per-step max-abs on A' and P' over non-ambiguous cells
+# split-bf16 DFT form: the state after the growth mapping (a potential error of
+# 2e-5 amplified by up to dt max|G'| = 24), and the alpha-ambiguity band (above
+# the form's potential error)
+TOL_STATE_DFT = 5e-4
+AMB_TAU_DFT = 2e-5
 
 
 def dev(x):
@@ -45,3 +50,39 @@ def window(arr, y0, x0, h, w):
     ys = (y0 + np.arange(h)) % H
     xs = (x0 + np.arange(w)) % W
     return np.take(np.take(arr, ys, axis=-2), xs, axis=-1)
+
+
+def dilate(mask, r):
+    """Cells within distance r (disk, on the torus) of a True cell."""
+    H, W = mask.shape
+    out = np.zeros_like(mask)
+    ys, xs = np.nonzero(mask)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            if dy * dy + dx * dx <= r * r:
+                out[(ys + dy) % H, (xs + dx) % W] = True
+    return out
+
+
+def compare_evolve(r, A1, P1, r_oxy, tol):
+    """Max-abs errors of an operators iteration, over cells whose alpha decision
+    is not ambiguous and that lie farther than 2 r_oxy from a cell whose
+    organic-matter sum is within tau of eps (the penalizing area may differ
+    there)."""
+    amb = r["amb"]
+    bad = ((amb & 1) != 0) | dilate((amb & 4) != 0, 2 * r_oxy)
+    ok = ~bad
+    eA = float(np.abs(A1.astype(np.float64) - r["A"])[:, ok].max()) if ok.any() else 0.0
+    eP = float(np.abs(P1.astype(np.float64) - r["P"])[:, :, ok].max()) if ok.any() else 0.0
+    assert eA <= tol and eP <= tol, (eA, eP, int(bad.sum()))
+    return eA, eP, int(bad.sum())
+
+
+def device_window(t, y0, x0, h, w):
+    """Host copy of t[..., y0:y0+h, x0:x0+w] of a device tensor, with
+    wrap-around on the last two axes (gathered on the device)."""
+    import torch
+    H, W = t.shape[-2:]
+    ys = torch.arange(y0, y0 + h, device=t.device) % H
+    xs = torch.arange(x0, x0 + w, device=t.device) % W
+    return t.index_select(t.dim() - 2, ys).index_select(t.dim() - 1, xs).cpu().numpy()

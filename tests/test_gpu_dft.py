@@ -10,13 +10,12 @@ import pytest
 
 from paper_2304_05639_amd import inputs
 
-from gpu_helpers import dev, host
+from gpu_helpers import AMB_TAU_DFT, TOL_STATE_DFT, dev, host
 
 pytestmark = pytest.mark.gpu
 
 TOL_U = 2e-5
-TOL_STATE_DFT = 5e-4
-AMB_TAU = 2e-5        # alpha-ambiguity band for this form (above its potential error)
+AMB_TAU = AMB_TAU_DFT
 # The fp16 split keeps about 22 bits only for operands of magnitude 2^-3 and
 # above; smaller operands (the lo parts, and the small spectral products of
 # high frequencies) sit on fp16's subnormal grid 2^-24.  A tile's inverse

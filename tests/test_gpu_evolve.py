@@ -10,7 +10,7 @@ import pytest
 
 from paper_2304_05639_amd import inputs
 
-from gpu_helpers import TOL_STATE, dev, host, window
+from gpu_helpers import TOL_STATE, compare_evolve as _compare, dev, host, window
 
 pytestmark = pytest.mark.gpu
 
@@ -25,17 +25,6 @@ def L():
     return lenia
 
 
-def _dilate(mask, r):
-    H, W = mask.shape
-    out = np.zeros_like(mask)
-    ys, xs = np.nonzero(mask)
-    for dy in range(-r, r + 1):
-        for dx in range(-r, r + 1):
-            if dy * dy + dx * dx <= r * r:
-                out[(ys + dy) % H, (xs + dx) % W] = True
-    return out
-
-
 def _events(rng, n, H, W, nk=15):
     return [dict(mut_p=int(rng.integers(3)), mut_k=int(rng.integers(nk)),
                  mut_delta=float(np.float32(rng.uniform(-0.01, 0.01))), mut_y0=int(rng.integers(H)),
@@ -43,16 +32,6 @@ def _events(rng, n, H, W, nk=15):
                  pen_k=int(rng.integers(nk)),
                  pen_delta=float(np.float32((1 if p == 0 else -1) * rng.uniform(0, 0.01))))
             for _ in range(n)]
-
-
-def _compare(r, A1, P1, r_oxy, tol):
-    amb = r["amb"]
-    bad = ((amb & 1) != 0) | _dilate((amb & 4) != 0, 2 * r_oxy)
-    ok = ~bad
-    eA = float(np.abs(A1.astype(np.float64) - r["A"])[:, ok].max()) if ok.any() else 0.0
-    eP = float(np.abs(P1.astype(np.float64) - r["P"])[:, :, ok].max()) if ok.any() else 0.0
-    assert eA <= tol and eP <= tol, (eA, eP, int(bad.sum()))
-    return eA, eP, int(bad.sum())
 
 
 def _walls(H, W):
