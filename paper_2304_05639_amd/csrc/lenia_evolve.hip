@@ -18,15 +18,25 @@ constexpr int kMaxOxy = 16;
 
 // Wall cells of the state: A and all gene planes set to 0.  Each lane takes
 // kWallCells cells a grid apart, so that consecutive lanes read consecutive
-// mask bytes and write consecutive cells of every plane.
-constexpr int kWallCells = 4;
+// mask bytes and write consecutive cells of every plane; all of a lane's mask
+// bytes are read before any store, so their latencies overlap.
+constexpr int kWallCells = 8;
 
 __global__ __launch_bounds__(256) void walls_kernel(float* A, float* P, const uint8_t* walls,
                                                     uint32_t HW, int C, int NPG)
 {
     const uint32_t stride = gridDim.x * 256u;
-    for (uint32_t idx = blockIdx.x * 256u + threadIdx.x; idx < HW; idx += stride) {
-        if (!walls[idx]) continue;
+    const uint32_t i0 = blockIdx.x * 256u + threadIdx.x;
+    uint8_t m[kWallCells];
+#pragma unroll
+    for (int k = 0; k < kWallCells; ++k) {
+        const uint32_t idx = i0 + (uint32_t)k * stride;
+        m[k] = (idx < HW) ? walls[idx] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kWallCells; ++k) {
+        if (!m[k]) continue;
+        const uint32_t idx = i0 + (uint32_t)k * stride;
         for (int c = 0; c < C; ++c) A[(size_t)c * HW + idx] = 0.f;
         if (P)
             for (int q = 0; q < NPG; ++q) P[(size_t)q * HW + idx] = 0.f;
@@ -36,7 +46,10 @@ __global__ __launch_bounds__(256) void walls_kernel(float* A, float* P, const ui
 // out(x) = 1 if some cell d of the disk |d| <= r around x (on the torus) has
 // bit `bit` of src clear.  A tile of TY x TX cells stages, for each of its
 // TY + 2r rows, the prefix counts of clear cells over its TX + 2r columns, so
-// that each disk row is one difference of two counts.
+// that each disk row is one difference of two counts.  Each wave stages whole
+// rows (lanes are columns): the row's clear cells become two ballots over
+// columns [0, 64) and [64, TX + 2r) (TX = 64, 2r <= 32), and the prefix count
+// at column j is the number of set bits below j, the lane-masked bit count.
 constexpr int OXY_TY = 16, OXY_TX = 64;
 
 __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int bit, uint8_t* out,
@@ -44,7 +57,6 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
 {
     constexpr int MR = kMaxOxy;
     constexpr int RY = OXY_TY + 2 * MR, RX = OXY_TX + 2 * MR + 1;
-    __shared__ uint8_t clear[RY][RX];   // 1 where the staged cell's bit is clear
     __shared__ uint16_t zc[RY][RX];     // zc[row][j] = clear cells among columns [0, j)
     __shared__ int8_t half_width[MR + 1];
     const int tiles_x = (W + OXY_TX - 1) / OXY_TX;
@@ -57,23 +69,42 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
         while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
         half_width[dy] = (int8_t)w;
     }
-    // stage the tile and its r-cell halo (wrapped), all threads, row by row; a
-    // single wrap suffices unless the torus is smaller than tile + halo
-    const bool single_wrap = (H >= ny) && (W >= nx);
-    for (int i = threadIdx.x; i < ny * nx; i += 256) {
-        const int row = i / nx, col = i - row * nx;
-        int gy = ty0 + row - r, gx = tx0 + col - r;
-        wrap2(gy, gx, H, W, single_wrap);
-        clear[row][col] = ((src[(size_t)gy * W + gx] >> bit) & 1) ? 0 : 1;
-    }
-    __syncthreads();
-    // one thread per staged row: the prefix count over its columns
-    for (int row = threadIdx.x; row < ny; row += 256) {
-        uint16_t acc = 0;
-        zc[row][0] = 0;
-        for (int j = 0; j < nx; ++j) {
-            acc += clear[row][j];
-            zc[row][j + 1] = acc;
+    // stage the tile and its r-cell halo (wrapped): wave v takes rows v, v + 4,
+    // ..., all of its loads issued before the first ballot; a single wrap
+    // suffices unless the torus is smaller than tile + halo
+    {
+        constexpr int ROWS = (RY + 3) / 4;   // rows per wave at most
+        const bool single_wrap = (H >= ny) && (W >= nx);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const auto wrap = [&](int g, int n) {
+            return single_wrap ? g + ((g < 0) ? n : 0) - ((g >= n) ? n : 0) : ((g % n) + n) % n;
+        };
+        const bool in0 = lane < nx, in1 = 64 + lane < nx;
+        const int gx0 = wrap(tx0 + lane - r, W), gx1 = wrap(tx0 + 64 + lane - r, W);
+        uint8_t v0[ROWS], v1[ROWS];
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int row = wave + 4 * k;
+            v0[k] = v1[k] = 1u << bit;        // "set" (not clear) off the staged area
+            if (row < ny) {
+                const size_t base = (size_t)wrap(ty0 + row - r, H) * W;
+                if (in0) v0[k] = src[base + gx0];
+                if (in1) v1[k] = src[base + gx1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int row = wave + 4 * k;
+            if (row < ny) {
+                const uint64_t m0 = __ballot(((v0[k] >> bit) & 1) == 0);
+                const uint64_t m1 = __ballot(((v1[k] >> bit) & 1) == 0);
+                const unsigned below0 = __builtin_amdgcn_mbcnt_hi(
+                    (unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u));
+                const unsigned below1 = __builtin_amdgcn_mbcnt_hi(
+                    (unsigned)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
+                zc[row][lane] = (uint16_t)below0;
+                if (64 + lane <= nx) zc[row][64 + lane] = (uint16_t)(__popcll(m0) + below1);
+            }
         }
     }
     __syncthreads();
@@ -91,23 +122,25 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
     }
 }
 
-// Mutation, then penalization, of one iteration, on the new gene state.
+// Mutation, then penalization, of one iteration, on the new gene state, one
+// thread per cell.  The square's first row and column (sy0, sx0) come reduced
+// to [0, H) x [0, W), so a cell's offsets from them need one conditional add.
 __global__ __launch_bounds__(256) void events_kernel(float* P, const uint8_t* flags,
-                                                     const uint8_t* epen, int H, int W, int NK,
-                                                     lenia_event ev, float mut_add, int mut_half,
-                                                     float pen_add)
+                                                     const uint8_t* epen, int H, int W,
+                                                     int mut_plane, int sy0, int sx0, int side,
+                                                     float mut_add, int pen_plane, float pen_add)
 {
     const uint32_t HW = (uint32_t)H * (uint32_t)W;
     const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
     if (idx >= HW || !(flags[idx] & 1)) return;       // both act only where alpha = 1
-    const int y = (int)(idx / (uint32_t)W), x = (int)(idx - (uint32_t)y * W);
     if (mut_add != 0.f) {
-        // offsets of (y, x) from the square's first row / column, on the torus
-        const int oy = (((y - (ev.mut_y0 - mut_half)) % H) + H) % H;
-        const int ox = (((x - (ev.mut_x0 - mut_half)) % W) + W) % W;
-        if (oy < 2 * mut_half && ox < 2 * mut_half) P[(size_t)(ev.mut_p * NK + ev.mut_k) * HW + idx] += mut_add;
+        const int y = (int)(idx / (uint32_t)W), x = (int)(idx - (uint32_t)y * W);
+        int oy = y - sy0, ox = x - sx0;
+        oy += (oy < 0) ? H : 0;
+        ox += (ox < 0) ? W : 0;
+        if (oy < side && ox < side) P[(size_t)mut_plane * HW + idx] += mut_add;
     }
-    if (pen_add != 0.f && epen[idx]) P[(size_t)(ev.pen_p * NK + ev.pen_k) * HW + idx] += pen_add;
+    if (pen_add != 0.f && epen[idx]) P[(size_t)pen_plane * HW + idx] += pen_add;
 }
 
 }  // namespace lenia
@@ -230,8 +263,16 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
                 const lenia_event& ev = events[i - 1];
                 const float mut_add = mut ? (float)(evo->gamma_mut * (double)ev.mut_delta) : 0.f;
                 const float pen_add = pen ? (float)(evo->gamma_pen * (double)ev.pen_delta) : 0.f;
-                hipLaunchKernelGGL(events_kernel, dim3(cell_blocks), dim3(256), 0, s, nP, p->evo_flags,
-                                   p->evo_epen, w.H, w.W, w.NK, ev, mut_add, evo->mut_half, pen_add);
+                // the square's first row and column on the torus
+                const int64_t y0 = ((int64_t)ev.mut_y0 - evo->mut_half) % w.H;
+                const int64_t x0 = ((int64_t)ev.mut_x0 - evo->mut_half) % w.W;
+                // an operator that is off leaves its (unchecked) fields unused
+                const int mut_plane = mut ? ev.mut_p * w.NK + ev.mut_k : 0;
+                const int pen_plane = pen ? ev.pen_p * w.NK + ev.pen_k : 0;
+                hipLaunchKernelGGL(events_kernel, dim3(cell_blocks), dim3(256), 0, s, nP,
+                                   p->evo_flags, p->evo_epen, w.H, w.W, mut_plane,
+                                   (int)(y0 < 0 ? y0 + w.H : y0), (int)(x0 < 0 ? x0 + w.W : x0),
+                                   2 * evo->mut_half, mut_add, pen_plane, pen_add);
             }
             e = hipGetLastError();
             if (e != hipSuccess) return hip_fail(e, "operator launch");
