@@ -58,17 +58,9 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
     constexpr int MR = kMaxOxy;
     constexpr int RY = OXY_TY + 2 * MR, RX = OXY_TX + 2 * MR + 1;
     __shared__ uint16_t zc[RY][RX];     // zc[row][j] = clear cells among columns [0, j)
-    __shared__ int8_t half_width[MR + 1];
     const int tiles_x = (W + OXY_TX - 1) / OXY_TX;
     const int ty0 = (blockIdx.x / tiles_x) * OXY_TY, tx0 = (blockIdx.x % tiles_x) * OXY_TX;
     const int ny = OXY_TY + 2 * r, nx = OXY_TX + 2 * r;
-    if (threadIdx.x <= (unsigned)r) {
-        // largest w with w^2 + dy^2 <= r^2
-        const int dy = threadIdx.x;
-        int w = 0;
-        while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
-        half_width[dy] = (int8_t)w;
-    }
     // stage the tile and its r-cell halo (wrapped): wave v takes rows v, v + 4,
     // ..., all of its loads issued before the first ballot; a single wrap
     // suffices unless the torus is smaller than tile + halo
@@ -108,17 +100,34 @@ __global__ __launch_bounds__(256) void disk_clear_kernel(const uint8_t* src, int
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < OXY_TY * OXY_TX; i += 256) {
-        const int ly = i / OXY_TX, lx = i % OXY_TX;
-        const int gy = ty0 + ly, gx = tx0 + lx;
-        if (gy >= H || gx >= W) continue;
-        int hit = 0;
-        for (int dy = -r; dy <= r; ++dy) {
-            const int w = half_width[dy < 0 ? -dy : dy];
-            const int row = ly + r + dy, c0 = lx + r - w, c1 = lx + r + w + 1;
-            hit |= (zc[row][c1] - zc[row][c0]) > 0;
+    // the thread's cells: column lx, rows ly0, ly0 + 4, ..., all tested together
+    // so that the counts of one disk row are read in one round trip; the disk
+    // row dy spans columns [lx - w, lx + w], w the largest with w^2 + dy^2 <= r^2
+    // (uniform, updated as dy runs from -r to r)
+    constexpr int NQ = OXY_TY / 4;
+    const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
+    bool hit[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) hit[q] = false;
+    int w = 0;
+    for (int dy = -r; dy <= r; ++dy) {
+        while ((w + 1) * (w + 1) + dy * dy <= r * r) ++w;
+        while (w * w + dy * dy > r * r) --w;
+        const int c0 = lx + r - w, c1 = lx + r + w + 1;
+        uint16_t z0[NQ], z1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int row = ly0 + 4 * q + r + dy;
+            z0[q] = zc[row][c0];
+            z1[q] = zc[row][c1];
         }
-        out[(size_t)gy * W + gx] = (uint8_t)hit;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) hit[q] = hit[q] || (z1[q] != z0[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int gy = ty0 + ly0 + 4 * q, gx = tx0 + lx;
+        if (gy < H && gx < W) out[(size_t)gy * W + gx] = (uint8_t)hit[q];
     }
 }
 
