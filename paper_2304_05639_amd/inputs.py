@@ -284,6 +284,22 @@ def test_world(H: int, W: int, seed: int, n_blobs: Optional[int] = None,
                            dt=dt, name=f"test-{H}x{W}-s{seed}")
 
 
+def band_and_block_world(H: int, W: int, seed: int, band_width: int = 4) -> World:
+    """A world whose organic matter has a thin and a thick part: uniform random
+    matter in a horizontal band of band_width rows (rows [H/5, H/5 +
+    band_width), columns [W/20, 11W/20)) and in a block (rows [H/2, 15H/16),
+    columns [5W/8, 15W/16)), nothing elsewhere; genes as in localized_world.
+    Draw order: localized_world's with no blobs, then random((3, H, W)) of
+    which the band and the block are kept."""
+    rng = np.random.default_rng(seed)
+    w = localized_world(rng, H, W, 0, name=f"band-block-{H}x{W}-s{seed}")
+    mask = np.zeros((H, W), bool)
+    mask[H // 5:H // 5 + band_width, W // 20:11 * W // 20] = True
+    mask[H // 2:15 * H // 16, 5 * W // 8:15 * W // 16] = True
+    w.A = (rng.random((3, H, W)).astype(np.float32) * mask).astype(np.float32)
+    return w
+
+
 # ---- worlds too large to draw on the host -----------------------------------
 
 def large_world(H: int, W: int, seed: int, n_channels: int = 3) -> World:

@@ -100,6 +100,46 @@ def test_evolve_mutation_square_across_the_seam(L):
     assert np.array_equal(P1, want)
 
 
+@pytest.mark.parametrize("H,W,r_oxy,seed,world", [
+    (96, 192, 14, 821, "band"),
+    (96, 192, 16, 822, "band"),     # the largest radius
+    (96, 90, 16, 823, "band"),      # torus narrower than the disk test's tile + halo (wrap by modulo)
+    (100, 150, 13, 825, "band"),    # ragged in both directions
+    (96, 128, 0, 811, "blobs"),     # the disk is the cell itself
+    (33, 70, 2, 814, "blobs"),
+])
+def test_evolve_penalizing_area_radii(L, oracle, H, W, r_oxy, seed, world):
+    """One iteration with penalization and mutation against the oracle's evolve
+    step, at the edge radii of the penalizing area and on tori where the disk
+    test's tiles wrap or are ragged.  The band worlds have a thin band of
+    matter, whose organic region holds no disk of radius r_oxy, and a thick
+    block that does, so the penalizing area covers some alpha cells and not
+    others and its shape decides the result."""
+    import torch
+    if world == "band":
+        w = inputs.band_and_block_world(H, W, seed)
+    else:
+        w = inputs.test_world(H, W, seed=seed, n_blobs=max(1, H * W // 400))
+    d = oracle.Desc.from_world(w)
+    plan = L.Plan(w)
+    ev = _events(np.random.default_rng(seed), 1, H, W)[0]
+    mut_half = min(6, H // 2, W // 2)
+    A32, P32 = w.A.astype(np.float32), w.P.astype(np.float32)
+    A1, P1 = plan.step_evolve(dev(A32), dev(P32), gamma_mut=5.0, mut_half=mut_half, gamma_pen=0.2,
+                              r_oxy=r_oxy, events=[ev])
+    torch.cuda.synchronize()
+    r = oracle.evolve_step(d, A32, P32, gamma_mut=5.0, mut_half=mut_half, gamma_pen=0.2,
+                           r_oxy=r_oxy, event=ev)
+    alpha = (r["flags"] & 1) != 0
+    pen = int(((r["epen"] != 0) & alpha).sum())
+    eA, eP, n_bad = _compare(r, host(A1), host(P1), r_oxy, TOL_STATE)
+    print(f"{world} {H}x{W} r_oxy={r_oxy}: errA {eA:.2e} errP {eP:.2e} excluded {n_bad} "
+          f"penalized {pen} of {int(alpha.sum())} alpha cells", flush=True)
+    assert pen > 0
+    if world == "band":
+        assert pen < int(alpha.sum())
+
+
 def test_evolve_rejects(L):
     import torch
     w = inputs.test_world(32, 32, seed=804, n_blobs=1)
