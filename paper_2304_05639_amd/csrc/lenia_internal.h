@@ -100,6 +100,9 @@ struct WorldArgs {
     uint8_t* flags_out;    // [H][W] or null: bit 0 alpha, bit 1 sum_k u_k > eps (the
                            // organic-matter mask of the penalization); disables the
                            // tile shortcuts, which never form the potentials
+    uint8_t* p_zero;       // [n_tiles] or null: 1 where P_out is known to hold 0 on the
+                           // tile in every gene plane (set by a tile that writes its
+                           // genes as 0, cleared by one that writes them otherwise)
     const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
     const float* wt;       // [n_orbits][C][8] the same weights by (orbit, source, slot)
     int H, W;
@@ -136,5 +139,7 @@ batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx);
 int step_tile_candidates(int table, int R, int* ty, int* tx, int max);
 hipError_t launch_fill_synthetic(float* A, size_t nA, float* P, size_t plane, int nk,
                                  hipStream_t s);
+// p[0, n) = 0 (a kernel, so that the call can sit in a captured graph)
+hipError_t launch_clear_bytes(uint8_t* p, uint32_t n, hipStream_t s);
 
 }  // namespace lenia

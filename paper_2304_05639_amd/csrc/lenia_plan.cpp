@@ -621,6 +621,17 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
         WorldArgs a = w.args_template();
         a.tiles_x = tiles_of(w.W, p->tile_x);
         a.n_tiles = tiles_of(w.H, p->tile_y) * a.tiles_x;
+        // zero-gene tile flags of the two output buffers: known only for what
+        // this call has written, so cleared at its start
+        const bool zero_flags = upd && !saved && !conv_is_dft(p->conv) && n_steps > 2;
+        if (zero_flags) {
+            if (!w.p_zero) {
+                lenia_status zs = dmalloc(p, (void**)&w.p_zero, 2 * (size_t)a.n_tiles);
+                if (zs != LENIA_OK) return zs;
+            }
+            hipError_t ze = launch_clear_bytes(w.p_zero, 2u * (uint32_t)a.n_tiles, s);
+            if (ze != hipSuccess) return hip_fail(ze, "clearing tile flags");
+        }
         if (saved) {
             a.U_save = (float*)saved;
             a.alpha_save = (uint8_t*)saved + (size_t)w.NK * w.cells() * sizeof(float);
@@ -646,6 +657,7 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
             a.P = upd ? curP : P_in;
             a.A_out = nA;
             a.P_out = upd ? nP : nullptr;
+            a.p_zero = zero_flags ? w.p_zero + (nP == w.ws_P ? a.n_tiles : 0) : nullptr;
             hipError_t e;
             if (conv_is_dft(p->conv)) {
                 // potentials on the MFMA units into the saved buffer (or the

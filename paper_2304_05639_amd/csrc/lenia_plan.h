@@ -52,6 +52,8 @@ struct WorldPlan {
     float* dft_u = nullptr;        // [NK][H][W]
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
     float* ws_P = nullptr;         // [gene_types][NK][H][W] (gene update only)
+    uint8_t* p_zero = nullptr;     // [2][tiles] zero-gene tile flags of the caller's P
+                                   //   output and of ws_P (allocated on first use)
     size_t cells() const { return (size_t)H * W; }
     size_t a_elems() const { return (size_t)C * H * W; }
     size_t p_elems() const { return (size_t)gene_types * NK * H * W; }

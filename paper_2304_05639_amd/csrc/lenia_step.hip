@@ -267,9 +267,11 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
 // then).  c points at the
 // first cell in the staged tile (channel 0); cells past the torus edge are
 // skipped.  Planes are the outer loop, so each plane's descriptor is used for
-// all the cells and then dropped.
+// all the cells and then dropped.  With genes = false the gene planes, known
+// to hold 0 on the tile already, are left alone.
 template <class T, int Q, class L, int NPG>
-__device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const float* c, int gy, int gx)
+__device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const float* c, int gy, int gx,
+                                                 bool genes = true)
 {
     const size_t HW = (size_t)wd.H * wd.W;
     const uint32_t pb = 4u * (uint32_t)HW;
@@ -287,12 +289,14 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
         for (int q = 0; q < Q; ++q)
             if (in[q]) pst(pl, ob[q], clip01(c[ch * L::CHS + q * L::RS]));
     }
+    if (genes) {
 #pragma unroll
-    for (int p = 0; p < NPG; ++p) {
-        const plane_t pl = plane(wd.P_out + (size_t)p * HW, pb);
+        for (int p = 0; p < NPG; ++p) {
+            const plane_t pl = plane(wd.P_out + (size_t)p * HW, pb);
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (in[q]) pst(pl, ob[q], 0.f);
+            for (int q = 0; q < Q; ++q)
+                if (in[q]) pst(pl, ob[q], 0.f);
+        }
     }
     if (wd.alpha_save) {
 #pragma unroll
@@ -538,7 +542,11 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     // u_k is at most org_thr, so the sum is below eps and both flags are 0.
     const bool may_skip = (mode == MODE_LOCAL_UPDATE) && (wd.U_save == nullptr);
     const bool want_flags = (wd.flags_out != nullptr);
-    if (may_skip && threadIdx.x == 0) *tile_flag = 0;
+    // bit 30 of the tile flag: the output's gene planes already hold 0 on this
+    // tile (thread 0 reads the flag here and updates it after the last barrier)
+    constexpr int kGenesZero = 1 << 30;
+    if (may_skip && threadIdx.x == 0)
+        *tile_flag = (wd.p_zero != nullptr && wd.p_zero[tile] != 0) ? kGenesZero : 0;
     int wave_bits = 0;   // bit c < C: some window value of channel c above skip_thr
                          // (above org_thr with flags); bit C: some value of gene
                          // plane 0 above eps (without flags)
@@ -620,15 +628,18 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     if (may_skip) {
         if ((threadIdx.x & 63) == 0 && wave_bits != 0) atomicOr(tile_flag, wave_bits);
         __syncthreads();
-        if (want_flags ? (*tile_flag == 0) : (*tile_flag != (2 << T::C) - 1)) {
+        const int bits = *tile_flag & ((2 << T::C) - 1);
+        if (want_flags ? (bits == 0) : (bits != (2 << T::C) - 1)) {
             // an empty channel or a dead gene plane (with flags: every channel
             // empty): alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
             write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
-                                           x0 + lx);
+                                           x0 + lx, (*tile_flag & kGenesZero) == 0);
+            if (wd.p_zero != nullptr && threadIdx.x == 0) wd.p_zero[tile] = 1;
             return;
         }
+        if (wd.p_zero != nullptr && threadIdx.x == 0) wd.p_zero[tile] = 0;
     }
 
     // 2. potentials of the thread's cells, 3. their epilogues
@@ -851,6 +862,19 @@ __device__ __forceinline__ float hash01(uint32_t x)
     x *= 0x846ca68bU;
     x ^= x >> 16;
     return (float)(x >> 8) * (1.0f / 16777216.0f);
+}
+
+__global__ __launch_bounds__(256) void fill_bytes_kernel(uint8_t* p, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_clear_bytes(uint8_t* p, uint32_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_bytes_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
 }
 
 __global__ void fill_synthetic_kernel(float* A, size_t nA, float* P, size_t plane, int nk)
