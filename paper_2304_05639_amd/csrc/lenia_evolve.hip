@@ -228,6 +228,23 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
         a.tiles_x = (w.W + p->tile_x - 1) / p->tile_x;
         a.n_tiles = ((w.H + p->tile_y - 1) / p->tile_y) * a.tiles_x;
         a.flags_out = p->evo_flags;
+        // zero-gene tile flags of the two output buffers, as in lenia_step (the
+        // walls only write zeros and the events only touch cells where alpha
+        // holds, which lie in tiles that write their genes, so neither breaks
+        // them)
+        const bool zero_flags = !conv_is_dft(p->conv) && n_steps > 2;
+        if (zero_flags) {
+            if (!w.p_zero) {
+                void* q = nullptr;
+                if (hipMalloc(&q, 2 * (size_t)a.n_tiles) != hipSuccess)
+                    return set_error(LENIA_ERR_OUT_OF_MEMORY, "tile flags");
+                p->allocations.push_back(q);
+                p->ws_bytes += 2 * (size_t)a.n_tiles;
+                w.p_zero = (uint8_t*)q;
+            }
+            e = launch_clear_bytes(w.p_zero, 2u * (uint32_t)a.n_tiles, s);
+            if (e != hipSuccess) return hip_fail(e, "clearing tile flags");
+        }
         const int oxy_tiles = ((w.H + OXY_TY - 1) / OXY_TY) * ((w.W + OXY_TX - 1) / OXY_TX);
         float* curA = A_in;
         float* curP = P_in;
@@ -254,6 +271,7 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
             a.P = curP;
             a.A_out = nA;
             a.P_out = nP;
+            a.p_zero = zero_flags ? w.p_zero + (nP == w.ws_P ? a.n_tiles : 0) : nullptr;
             if (conv_is_dft(p->conv)) {
                 e = launch_dft_potentials(p, w, curA, w.dft_u, s);
                 if (e == hipSuccess) e = find_epilogue_launcher(p->table)(a, w.dft_u, w.mode, s);
