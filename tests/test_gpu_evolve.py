@@ -203,6 +203,28 @@ def test_evolve_full_size_sampled_windows(L, oracle):
         _compare(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw), r_oxy, TOL_STATE)
 
 
+def test_evolve_long_call_matches_single_iterations(L):
+    """12 iterations with walls, mutation and penalization in one call equal 12
+    single calls, bitwise, with the caller's output buffers starting as NaN
+    (the zero-gene tile flags act from the third step of a call)."""
+    import torch
+    H, W = 80, 128
+    w = inputs.test_world(H, W, seed=808, n_blobs=6)
+    plan = L.Plan(w)
+    walls = torch.tensor(_walls(H, W), device="cuda")
+    evs = _events(np.random.default_rng(808), 12, H, W)
+    kw = dict(walls=walls, gamma_mut=5.0, mut_half=6, gamma_pen=0.2, r_oxy=3)
+    A, P = dev(w.A), dev(w.P)
+    B, Q = A.clone(), P.clone()
+    for t in range(12):
+        B, Q = plan.step_evolve(B, Q, events=[evs[t]], **kw)
+    A1 = torch.full_like(A, float("nan"))
+    P1 = torch.full_like(P, float("nan"))
+    plan.step_evolve(A.clone(), P.clone(), A1, P1, n_steps=12, events=evs, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, B) and torch.equal(P1, Q)
+
+
 def test_evolve_multi_step_call_matches_single_steps(L):
     """n iterations in one call (ping-pong buffers, in place and out of place)
     equal one call per iteration with the same events, bitwise."""

@@ -166,6 +166,37 @@ def test_multistep_schedules_agree(L):
     assert np.array_equal(host(A), w.A) and np.array_equal(host(P), w.P)
 
 
+def test_long_call_matches_single_steps(L):
+    """40 steps in one call equal 40 single-step calls, bitwise, in and out of
+    place, on a sparse world whose tiles go from empty to active and back.
+    In a call of more than two steps, a tile that takes the alpha = 0
+    shortcut skips rewriting gene planes that its output buffer already holds
+    as 0.  The caller's output buffer starts as NaN, so a skipped write that
+    the call did not make itself would show."""
+    import torch
+    w = inputs.test_world(96, 160, seed=118, n_blobs=8)
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    a, p = A.clone(), P.clone()
+    for _ in range(40):
+        a, p = plan.step(a, p)
+    A1 = torch.full_like(A, float("nan"))
+    P1 = torch.full_like(P, float("nan"))
+    plan.step(A, P, A_out=A1, P_out=P1, n_steps=40)
+    Ai, Pi = A.clone(), P.clone()
+    plan.step(Ai, Pi, A_out=Ai, P_out=Pi, n_steps=39)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, a) and torch.equal(P1, p)
+    b, q = A.clone(), P.clone()
+    for _ in range(39):
+        b, q = plan.step(b, q)
+    torch.cuda.synchronize()
+    assert torch.equal(Ai, b) and torch.equal(Pi, q)
+    # the trajectory does cross the shortcut: some cells alive, some tiles empty
+    alive = float((p[0, 0] > 0).float().mean())
+    assert 0.0 < alive < 0.9, alive
+
+
 def test_saved_potentials_and_alpha(L, oracle):
     w = inputs.test_world(80, 100, seed=118, n_blobs=6)
     d = oracle.Desc.from_world(w)
