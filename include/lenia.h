@@ -159,6 +159,11 @@ LENIA_API lenia_status lenia_plan_batched(const lenia_desc* descs, int32_t n_wor
  * lenia_saved_bytes() bytes that receives the step's potentials u_k
  * (float[NK][H][W]) followed by the alpha mask (uint8[H][W]), for
  * lenia_backward.
+ * A call of more than two steps that updates genes keeps one byte per tile
+ * and output buffer (2 bytes per tile, allocated on first use, cleared at the
+ * start of the call): a tile whose genes are provably 0 does not rewrite gene
+ * planes that this call already wrote as 0 there.  The results are the same
+ * as with every plane written.
  */
 LENIA_API lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in,
                         float* A_out, float* P_out, int32_t n_steps, void* saved,
@@ -234,7 +239,8 @@ typedef struct {
  * n_steps iterations of the above.  Buffers as for lenia_step (in place or
  * out of place), except that the wall cells of (A_in, P_in) are zeroed in
  * place first.  events: host array of n_steps entries (may be NULL when both
- * rates are 0).  Workspace of 3 bytes per cell allocated on first use.
+ * rates are 0).  Workspace of 3 bytes per cell allocated on first use, and the
+ * tile bytes of lenia_step for calls of more than two steps.
  * Ring-decomposed kernels and batched plans: LENIA_ERR_UNSUPPORTED.
  */
 LENIA_API lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_in, float* A_out,
