@@ -99,6 +99,25 @@ def test_ring_multi_step_call_matches_single_steps(L):
     assert torch.equal(Ai, B) and torch.equal(Pi, Q)
 
 
+def test_ring_long_call_matches_single_steps(L):
+    """24 steps in one call equal 24 single-step calls, bitwise, with the
+    caller's output buffers starting as NaN: from the third step of a call a
+    tile that takes the alpha = 0 shortcut skips rewriting the 135 gene planes
+    its output buffer already holds as 0."""
+    import torch
+    w = inputs.ring_test_world(96, 128, seed=615, n_blobs=6)
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    B, Q = A.clone(), P.clone()
+    for _ in range(24):
+        B, Q = plan.step(B, Q)
+    A1 = torch.full_like(A, float("nan"))
+    P1 = torch.full_like(P, float("nan"))
+    plan.step(A, P, A_out=A1, P_out=P1, n_steps=24)
+    torch.cuda.synchronize()
+    assert torch.equal(A1, B) and torch.equal(P1, Q)
+
+
 def test_ring_unsupported_calls(L):
     import torch
     w = inputs.ring_test_world(32, 32, seed=615, n_blobs=1)
