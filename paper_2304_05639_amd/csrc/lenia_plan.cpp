@@ -730,13 +730,32 @@ lenia_status fill_batch_tables(lenia_plan_t p, float* const* A, float* const* P,
 {
     const int n = (int)p->worlds.size();
     std::vector<WorldArgs> t0(n), t1(n);
+    // zero-gene tile flags (as in lenia_step), two arrays per world, cleared by
+    // lenia_step_batched at the start of every call
+    size_t zbytes = 0;
+    for (int i = 0; i < n; ++i) {
+        const WorldPlan& w = p->worlds[i];
+        if (w.mode == MODE_LOCAL_UPDATE)
+            zbytes += 2 * (size_t)tiles_of(w.W, p->tile_x) * tiles_of(w.H, p->tile_y);
+    }
+    if (zbytes && !p->batch_zero) {
+        lenia_status zs = dmalloc(p, (void**)&p->batch_zero, zbytes);
+        if (zs != LENIA_OK) return zs;
+        p->batch_zero_bytes = zbytes;
+    }
+    size_t zoff = 0;
     for (int i = 0; i < n; ++i) {
         WorldPlan& w = p->worlds[i];
         WorldArgs a = w.args_template();
         a.tiles_x = tiles_of(w.W, p->tile_x);
         a.n_tiles = tiles_of(w.H, p->tile_y) * a.tiles_x;
         const bool upd = (w.mode == MODE_LOCAL_UPDATE);
+        if (upd && p->batch_zero) {
+            a.p_zero = p->batch_zero + zoff;
+            zoff += 2 * (size_t)a.n_tiles;
+        }
         WorldArgs b = a;
+        if (a.p_zero) b.p_zero = a.p_zero + a.n_tiles;
         a.A = A[i];
         a.P = (w.mode == MODE_GLOBAL) ? nullptr : P[i];
         a.A_out = w.ws_A;
@@ -818,6 +837,11 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
             }
             p->graph_A = va;
             p->graph_P = vp;
+        }
+        // the tile flags only describe what this call writes
+        if (p->batch_zero) {
+            e = launch_clear_bytes(p->batch_zero, (uint32_t)p->batch_zero_bytes, s);
+            if (e != hipSuccess) return hip_fail(e, "clearing tile flags");
         }
         for (int i = 0; i + 1 < n_steps && e == hipSuccess; i += 2) e = hipGraphLaunch(p->graph, s);
         if (e == hipSuccess && (n_steps % 2 == 1)) {

@@ -87,6 +87,8 @@ struct lenia_plan_ {
     lenia::WorldArgs* d_tables[2] = {nullptr, nullptr};   // phase 0: X -> ws, 1: ws -> X
     int2* d_items = nullptr;
     int n_items = 0;
+    uint8_t* batch_zero = nullptr;    // zero-gene tile flags of every world's two output
+    size_t batch_zero_bytes = 0;      //   buffers (ws in phase 0, the caller's in phase 1)
     std::vector<float*> graph_A, graph_P;                 // pointer set of the graph
     hipGraphExec_t graph = nullptr;
     hipStream_t capture_stream = nullptr;                 // private stream used for capture

@@ -47,6 +47,29 @@ def test_batched_equals_single(L, n_steps):
         assert torch.equal(a, A) and torch.equal(p, P), (w.name, n_steps)
 
 
+@pytest.mark.parametrize("n_steps", [19, 20])
+def test_batched_long_call_equals_single_steps(L, n_steps):
+    """A batched call of many steps equals, for every world, a chain of
+    single-step calls (which keep every gene write), bitwise: from the third
+    step of a call a tile that takes the alpha = 0 shortcut skips rewriting
+    gene planes its output buffer already holds as 0."""
+    import torch
+    worlds = _worlds()
+    bp = L.BatchedPlan(worlds)
+    tile = (bp.info().tile_y, bp.info().tile_x)
+    As = [dev(w.A) for w in worlds]
+    Ps = [dev(w.P) for w in worlds]
+    bp.step(As, Ps, n_steps=n_steps)
+    torch.cuda.synchronize()
+    for w, A, P in zip(worlds, As, Ps):
+        sp = L.Plan(w, tile=tile)
+        a, p = dev(w.A), dev(w.P)
+        for _ in range(n_steps):
+            a, p = sp.step(a, p)
+        torch.cuda.synchronize()
+        assert torch.equal(a, A) and torch.equal(p, P), (w.name, n_steps)
+
+
 def test_batched_many_tiles_equals_single(L):
     """More than 8 runs of 512 work items, so that blocks map to items through
     the XCD run permutation and its tail: still every world bit for bit."""
