@@ -172,7 +172,9 @@ LENIA_API lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float
 /* Advances every world of a batched plan by n_steps, in place: A[i], P[i] are
  * device pointers of world i (host arrays of n_worlds pointers).  The steps
  * run as one launch per step over a (world, tile) work list,
- * captured once into a HIP graph per pointer set and replayed. */
+ * captured once into a HIP graph per pointer set and replayed.  The
+ * zero-gene tile bytes of lenia_step (2 per tile of every world, allocated
+ * on the first call) are cleared by a kernel before the replays. */
 LENIA_API lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P,
                                 int32_t n_steps, void* stream);
 
