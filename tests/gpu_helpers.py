@@ -8,6 +8,13 @@ TOL_STATE = 1e-5      # per-step max-abs on A' and P' over non-ambiguous cells
 # the form's potential error)
 TOL_STATE_DFT = 5e-4
 AMB_TAU_DFT = 2e-5
+# A comparison must compare something: at most this fraction of the cells may
+# be left out as ambiguous.  On the test worlds the oracle flags at most 0.7%
+# of the cells at tau = 1e-5 and 1.1% at tau = 2e-5 (bit 0, and for the
+# operators the 2 r_oxy neighbourhood of bit 2); a 48 x 48 window of a large
+# world may hold more of them locally.
+MAX_EXCLUDED = 0.02
+MAX_EXCLUDED_WINDOW = 0.05
 
 
 def dev(x):
@@ -29,15 +36,22 @@ def gpu_step(plan, A, P, n_steps=1, saved=None):
     return host(A1), (host(P1) if P1 is not None else None)
 
 
-def compare_step(oracle_res, A1, P1, tol=TOL_STATE):
+def check_excluded(excluded, max_excluded):
+    """At least one cell is compared, and at most max_excluded of them left out."""
+    n, n_ex = excluded.size, int(excluded.sum())
+    assert n_ex < n, f"every one of the {n} cells is excluded: nothing compared"
+    assert n_ex <= max_excluded * n, \
+        f"{n_ex} of {n} cells excluded as ambiguous (bound {max_excluded:.0%})"
+
+
+def compare_step(oracle_res, A1, P1, tol=TOL_STATE, max_excluded=MAX_EXCLUDED):
     """Max-abs errors over cells whose alpha decision is not ambiguous."""
     ok = (oracle_res["amb"] & 1) == 0
-    eA = np.abs(A1.astype(np.float64) - oracle_res["A"])[:, ok]
-    errA = float(eA.max()) if eA.size else 0.0
+    check_excluded(~ok, max_excluded)
+    errA = float(np.abs(A1.astype(np.float64) - oracle_res["A"])[:, ok].max())
     errP = 0.0
     if P1 is not None and oracle_res["P"] is not None:
-        eP = np.abs(P1.astype(np.float64) - oracle_res["P"])[:, :, ok]
-        errP = float(eP.max()) if eP.size else 0.0
+        errP = float(np.abs(P1.astype(np.float64) - oracle_res["P"])[:, :, ok].max())
     n_amb = int((~ok).sum())
     assert errA <= tol, f"A' max-abs error {errA:.3e} > {tol} ({n_amb} ambiguous cells)"
     assert errP <= tol, f"P' max-abs error {errP:.3e} > {tol} ({n_amb} ambiguous cells)"
@@ -64,7 +78,7 @@ def dilate(mask, r):
     return out
 
 
-def compare_evolve(r, A1, P1, r_oxy, tol):
+def compare_evolve(r, A1, P1, r_oxy, tol, max_excluded=MAX_EXCLUDED):
     """Max-abs errors of an operators iteration, over cells whose alpha decision
     is not ambiguous and that lie farther than 2 r_oxy from a cell whose
     organic-matter sum is within tau of eps (the penalizing area may differ
@@ -72,8 +86,9 @@ def compare_evolve(r, A1, P1, r_oxy, tol):
     amb = r["amb"]
     bad = ((amb & 1) != 0) | dilate((amb & 4) != 0, 2 * r_oxy)
     ok = ~bad
-    eA = float(np.abs(A1.astype(np.float64) - r["A"])[:, ok].max()) if ok.any() else 0.0
-    eP = float(np.abs(P1.astype(np.float64) - r["P"])[:, :, ok].max()) if ok.any() else 0.0
+    check_excluded(bad, max_excluded)
+    eA = float(np.abs(A1.astype(np.float64) - r["A"])[:, ok].max())
+    eP = float(np.abs(P1.astype(np.float64) - r["P"])[:, :, ok].max())
     assert eA <= tol and eP <= tol, (eA, eP, int(bad.sum()))
     return eA, eP, int(bad.sum())
 

@@ -66,8 +66,9 @@ def _rel(a, b, mask=None):
     if mask is not None:
         d = d[..., mask]
         b = b[..., mask]
-    scale = max(np.abs(b).max() if b.size else 0.0, 1e-30)
-    return float(d.max() / scale) if d.size else 0.0
+    assert d.size > 0, "no entry left to compare"
+    scale = max(np.abs(b).max(), 1e-30)
+    return float(d.max() / scale)
 
 
 def smooth_world(H, W, seed, genotype_update=1):

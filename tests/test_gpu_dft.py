@@ -10,7 +10,7 @@ import pytest
 
 from paper_2304_05639_amd import inputs
 
-from gpu_helpers import AMB_TAU_DFT, TOL_STATE_DFT, dev, host
+from gpu_helpers import AMB_TAU_DFT, MAX_EXCLUDED, TOL_STATE_DFT, check_excluded, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,7 @@ def test_dft_potentials_and_state(L, oracle, H, W, seed, R, conv):
     r = oracle.step(d, w.A, w.P)
     eu = float(np.abs(u - r["U"]).max())
     ok = (r["amb"] & 1) == 0
+    check_excluded(~ok, MAX_EXCLUDED)
     eA = float(np.abs(A1 - r["A"])[:, ok].max())
     eP = float(np.abs(P1 - r["P"])[:, :, ok].max())
     print(f"DFT conv={conv} {H}x{W} R={R}: u err {eu:.2e}  A' err {eA:.2e}  P' err {eP:.2e}  "

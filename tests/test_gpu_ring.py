@@ -7,7 +7,7 @@ import pytest
 
 from paper_2304_05639_amd import inputs
 
-from gpu_helpers import TOL_STATE, compare_step, dev, gpu_step, host, window
+from gpu_helpers import MAX_EXCLUDED_WINDOW, TOL_STATE, compare_step, dev, gpu_step, host, window
 
 pytestmark = pytest.mark.gpu
 
@@ -171,6 +171,7 @@ def test_ring_full_size_sampled_windows(L, oracle, ring_world_4096, t0):
         rr = dict(A=r["A"][(slice(None),) + inner], P=r["P"][(slice(None), slice(None)) + inner],
                   amb=r["amb"][inner])
         active += int((r["alpha"][inner] == 1).sum())
-        compare_step(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw), tol=TOL_RING)
+        compare_step(rr, window(A1h, y0, x0, hw, hw), window(P1h, y0, x0, hw, hw), tol=TOL_RING,
+                     max_excluded=MAX_EXCLUDED_WINDOW)
     print(f"ring 4096^2 at t={t0}: {len(starts)} windows, {active} cells with alpha = 1")
     assert active > 0
