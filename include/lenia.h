@@ -55,7 +55,9 @@ typedef enum {
     LENIA_ERR_UNSUPPORTED = 2,   /* valid, but outside what the kernels build */
     LENIA_ERR_OUT_OF_MEMORY = 3, /* device allocation failed                  */
     LENIA_ERR_HIP = 4,           /* a HIP runtime call or launch failed       */
-    LENIA_ERR_STATE = 5          /* call not valid for this plan              */
+    LENIA_ERR_STATE = 5,         /* call not valid for this plan              */
+    LENIA_ERR_NONFINITE = 6      /* LENIA_FLAG_CHECK_FINITE found a NaN or an
+                                    infinity in an input buffer              */
 } lenia_status;
 
 /* How the potentials u_k = K~_k * A are computed.  Every form computes the
@@ -118,6 +120,19 @@ typedef struct {
 
 #define LENIA_FLAG_AUTOTUNE 1u  /* time the tile candidates at plan time and
                                    cache the winner per (H, W, R, C, mode)       */
+#define LENIA_FLAG_CHECK_FINITE 2u
+                                /* debug checks on every call of the plan, before
+                                   anything else is enqueued: each caller buffer
+                                   must lie inside the device allocation that
+                                   holds it (host-side, from the allocation's
+                                   address range: LENIA_ERR_INVALID_ARG), and
+                                   every value of the input buffers (state,
+                                   genes, cotangents) must be finite (a device
+                                   scan, after which the call waits for its
+                                   stream: LENIA_ERR_NONFINITE).  The steps
+                                   assume finite inputs and do not check them
+                                   otherwise (a NaN fails every comparison and
+                                   the clips pass it on).                        */
 
 typedef struct lenia_plan_* lenia_plan_t;
 
@@ -248,6 +263,15 @@ typedef struct {
 LENIA_API lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_in, float* A_out,
                                          float* P_out, int32_t n_steps, const lenia_evolution* evo,
                                          const lenia_event* events, void* stream);
+
+/*
+ * Test hook for the failure paths of device allocation (not for production
+ * use): from now on, in this process, let `after` device allocations of the
+ * library through and make the `count` after them fail as if the device were
+ * out of memory (the call then returns LENIA_ERR_OUT_OF_MEMORY and leaves its
+ * plan as it was).  count <= 0 turns the hook off.
+ */
+LENIA_API void lenia_debug_fail_alloc(int32_t after, int32_t count);
 
 LENIA_API lenia_status lenia_plan_get_info(lenia_plan_t p, lenia_plan_info* info);
 LENIA_API lenia_status lenia_plan_destroy(lenia_plan_t p);

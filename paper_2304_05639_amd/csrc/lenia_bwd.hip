@@ -629,6 +629,130 @@ static bwd_launch_fn find_bwd(int table, int R, bool small)
     return nullptr;
 }
 
+// Adjoint workspace sizes of a world: ubar [NK][H][W], numbar [3NK][H][W]
+// (gene update only) and the per-tile shell-height partials, sized for the
+// larger tile count of the two gather tiles.
+static size_t bwd_part_tiles(const WorldPlan& w) { return (size_t)((w.W + 31) / 32) * ((w.H + 7) / 8); }
+
+static void bwd_ws_sizes(const WorldPlan& w, size_t sizes[3])
+{
+    sizes[0] = (size_t)w.NK * w.cells() * sizeof(float);
+    sizes[1] = (w.mode == MODE_LOCAL_UPDATE) ? 3 * (size_t)w.NK * w.cells() * sizeof(float) : 0;
+    sizes[2] = bwd_part_tiles(w) * w.NK * 3 * sizeof(float);
+}
+
+// The plan's adjoint workspaces, allocated on first use: all three or none, so
+// a failed allocation leaves the plan as it was and the next call tries again.
+static lenia_status ensure_bwd_ws(lenia_plan_t p, const WorldPlan& w)
+{
+    if (p->bw.ubar) return LENIA_OK;
+    size_t sizes[3];
+    bwd_ws_sizes(w, sizes);
+    void* q[3] = {nullptr, nullptr, nullptr};
+    for (int i = 0; i < 3; ++i) {
+        if (sizes[i] && device_alloc(&q[i], sizes[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j)
+                if (q[j]) (void)hipFree(q[j]);
+            return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
+        }
+    }
+    for (int i = 0; i < 3; ++i)
+        if (q[i]) {
+            p->allocations.push_back(q[i]);
+            p->ws_bytes += sizes[i];
+        }
+    p->bw.ubar = (float*)q[0];
+    p->bw.numbar = (float*)q[1];
+    p->bw.part = (float*)q[2];
+    p->bw.n_part = (int)bwd_part_tiles(w);
+    return LENIA_OK;
+}
+
+// Checks the plan and call arguments (nothing enqueued on error).
+static lenia_status bwd_validate(lenia_plan_t p, const float* A_t, const float* P_t,
+                                 const void* saved, const float* gA_next, const float* gP_next,
+                                 float* gA_t, float* gP_t, float* gbeta)
+{
+    if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
+    if (p->batched) return set_error(LENIA_ERR_STATE, "adjoint needs a single-world plan");
+    if (p->rings) return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint for ring-decomposed kernels");
+    const WorldPlan& w = p->worlds[0];
+    if (w.mode == MODE_GLOBAL) return set_error(LENIA_ERR_UNSUPPORTED, "adjoint needs localized genes");
+    const bool small = ((size_t)((w.H + 15) / 16) * ((w.W + 31) / 32) < 1024);
+    if (!find_bwd(p->table, p->R, small))
+        return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint kernel for this table / R");
+    if (!A_t || !P_t || !saved || !gA_next || !gA_t || !gP_t || !gbeta)
+        return set_error(LENIA_ERR_INVALID_ARG, "NULL argument (only gP_next may be NULL)");
+    const uintptr_t al = (uintptr_t)A_t | (uintptr_t)P_t | (uintptr_t)saved | (uintptr_t)gA_next |
+                         (uintptr_t)gA_t | (uintptr_t)gP_t | (uintptr_t)gbeta | (uintptr_t)gP_next;
+    if (al & 3) return set_error(LENIA_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
+    const void* ins[] = {A_t, P_t, saved, gA_next, gP_next};
+    for (const void* q : ins)
+        if (q && (q == (const void*)gA_t || q == (const void*)gP_t))
+            return set_error(LENIA_ERR_INVALID_ARG, "gA_t / gP_t must not alias an input");
+    if ((const void*)gA_t == (const void*)gP_t)
+        return set_error(LENIA_ERR_INVALID_ARG, "gA_t and gP_t must differ");
+    return LENIA_OK;
+}
+
+// LENIA_FLAG_CHECK_FINITE on the adjoint's buffers.
+static lenia_status bwd_debug_checks(lenia_plan_t p, const float* A_t, const float* P_t,
+                                     const void* saved, const float* gA_next, const float* gP_next,
+                                     float* gA_t, float* gP_t, float* gbeta, hipStream_t s)
+{
+    const WorldPlan& w = p->worlds[0];
+    const size_t ab = w.a_elems() * sizeof(float), pb = w.p_elems() * sizeof(float);
+    const DebugBuf db[] = {{A_t, ab, "A_t", true},
+                           {P_t, pb, "P_t", true},
+                           {saved, (size_t)w.NK * w.cells() * sizeof(float), "saved", true},
+                           {(const char*)saved + (size_t)w.NK * w.cells() * sizeof(float), w.cells(),
+                            "saved alpha", false},
+                           {gA_next, ab, "gA_next", true},
+                           {gP_next, pb, "gP_next", true},
+                           {gA_t, ab, "gA_t", false},
+                           {gP_t, pb, "gP_t", false},
+                           {gbeta, (size_t)w.NK * 3 * sizeof(float), "gbeta", true}};
+    return debug_checks(p, db, 9, s);
+}
+
+// Enqueues the three adjoint kernels with the given workspaces (every element
+// of them that a kernel reads is written earlier in the same call).
+static lenia_status bwd_enqueue(lenia_plan_t p, const float* A_t, const float* P_t,
+                                const void* saved, const float* gA_next, const float* gP_next,
+                                float* gA_t, float* gP_t, float* gbeta, float* ubar, float* numbar,
+                                float* part, hipStream_t s)
+{
+    const WorldPlan& w = p->worlds[0];
+    const bool small = ((size_t)((w.H + 15) / 16) * ((w.W + 31) / 32) < 1024);
+    const int kBwdTY = small ? 8 : 16, kBwdTX = 32;
+    bwd_launch_fn fn = find_bwd(p->table, p->R, small);
+    const int tiles_x = (w.W + kBwdTX - 1) / kBwdTX;
+    BwdArgs a{};
+    a.A = A_t;
+    a.P = P_t;
+    a.U = (const float*)saved;
+    a.alpha = (const uint8_t*)saved + (size_t)w.NK * w.cells() * sizeof(float);
+    a.gA1 = gA_next;
+    a.gP1 = gP_next;
+    a.gA = gA_t;
+    a.gP = gP_t;
+    a.ubar = ubar;
+    a.numbar = numbar;
+    a.part = part;
+    a.wt = w.d_wt;
+    a.bt = w.d_bt;
+    a.H = w.H;
+    a.W = w.W;
+    a.tiles_x = tiles_x;
+    a.n_tiles = tiles_x * ((w.H + kBwdTY - 1) / kBwdTY);
+    a.dt = (float)w.dt;
+    a.eps = eps_below(w.eps);
+    a.mode = w.mode;
+    hipError_t e = fn(a, w.d_nshells, gbeta, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return LENIA_OK;
+}
+
 }  // namespace lenia
 
 using namespace lenia;
@@ -639,80 +763,15 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
                                        float* gbeta, void* stream)
 {
     try {
-        if (!p) return set_error(LENIA_ERR_INVALID_ARG, "plan is NULL");
-        if (p->batched) return set_error(LENIA_ERR_STATE, "adjoint needs a single-world plan");
-        if (p->rings)
-            return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint for ring-decomposed kernels");
-        WorldPlan& w = p->worlds[0];
-        if (w.mode == MODE_GLOBAL)
-            return set_error(LENIA_ERR_UNSUPPORTED, "adjoint needs localized genes");
-        const bool small = ((size_t)((w.H + 15) / 16) * ((w.W + 31) / 32) < 1024);
-        const int kBwdTY = small ? 8 : 16, kBwdTX = 32;
-        bwd_launch_fn fn = find_bwd(p->table, p->R, small);
-        if (!fn) return set_error(LENIA_ERR_UNSUPPORTED, "no adjoint kernel for this table / R");
-        if (!A_t || !P_t || !saved || !gA_next || !gA_t || !gP_t || !gbeta)
-            return set_error(LENIA_ERR_INVALID_ARG, "NULL argument (only gP_next may be NULL)");
-        const uintptr_t al = (uintptr_t)A_t | (uintptr_t)P_t | (uintptr_t)saved |
-                             (uintptr_t)gA_next | (uintptr_t)gA_t | (uintptr_t)gP_t |
-                             (uintptr_t)gbeta | (uintptr_t)gP_next;
-        if (al & 3) return set_error(LENIA_ERR_INVALID_ARG, "buffers must be 4-byte aligned");
-        const void* ins[] = {A_t, P_t, saved, gA_next, gP_next};
-        for (const void* q : ins)
-            if (q && (q == (const void*)gA_t || q == (const void*)gP_t))
-                return set_error(LENIA_ERR_INVALID_ARG, "gA_t / gP_t must not alias an input");
-        if ((const void*)gA_t == (const void*)gP_t)
-            return set_error(LENIA_ERR_INVALID_ARG, "gA_t and gP_t must differ");
-        hipStream_t s = (hipStream_t)stream;
-        const int tiles_x = (w.W + kBwdTX - 1) / kBwdTX;
-        const int n_tiles = tiles_x * ((w.H + kBwdTY - 1) / kBwdTY);
-        // workspaces, allocated on first use
-        if (!p->bw.ubar) {
-            void* q = nullptr;
-            if (hipMalloc(&q, w.NK * w.cells() * sizeof(float)) != hipSuccess)
-                return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
-            p->allocations.push_back(q);
-            p->ws_bytes += w.NK * w.cells() * sizeof(float);
-            p->bw.ubar = (float*)q;
-            if (w.mode == MODE_LOCAL_UPDATE) {
-                if (hipMalloc(&q, 3 * w.NK * w.cells() * sizeof(float)) != hipSuccess)
-                    return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
-                p->allocations.push_back(q);
-                p->ws_bytes += 3 * w.NK * w.cells() * sizeof(float);
-                p->bw.numbar = (float*)q;
-            }
-            // sized for the larger tile count of the two gather tiles
-            const size_t max_tiles = (size_t)((w.W + 31) / 32) * ((w.H + 7) / 8);
-            if (hipMalloc(&q, max_tiles * w.NK * 3 * sizeof(float)) != hipSuccess)
-                return set_error(LENIA_ERR_OUT_OF_MEMORY, "adjoint workspace");
-            p->allocations.push_back(q);
-            p->ws_bytes += max_tiles * w.NK * 3 * sizeof(float);
-            p->bw.part = (float*)q;
-            p->bw.n_part = (int)max_tiles;
-        }
-        BwdArgs a{};
-        a.A = A_t;
-        a.P = P_t;
-        a.U = (const float*)saved;
-        a.alpha = (const uint8_t*)saved + (size_t)w.NK * w.cells() * sizeof(float);
-        a.gA1 = gA_next;
-        a.gP1 = gP_next;
-        a.gA = gA_t;
-        a.gP = gP_t;
-        a.ubar = p->bw.ubar;
-        a.numbar = p->bw.numbar;
-        a.part = p->bw.part;
-        a.wt = w.d_wt;
-        a.bt = w.d_bt;
-        a.H = w.H;
-        a.W = w.W;
-        a.tiles_x = tiles_x;
-        a.n_tiles = n_tiles;
-        a.dt = (float)w.dt;
-        a.eps = eps_below(w.eps);
-        a.mode = w.mode;
-        hipError_t e = fn(a, w.d_nshells, gbeta, s);
-        if (e != hipSuccess) return hip_fail(e, "adjoint launch");
-        return LENIA_OK;
+        lenia_status st = bwd_validate(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta);
+        if (st != LENIA_OK) return st;
+        const WorldPlan& w = p->worlds[0];
+        if ((st = bwd_debug_checks(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta,
+                                   (hipStream_t)stream)) != LENIA_OK)
+            return st;
+        if ((st = ensure_bwd_ws(p, w)) != LENIA_OK) return st;
+        return bwd_enqueue(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta, p->bw.ubar,
+                           p->bw.numbar, p->bw.part, (hipStream_t)stream);
     } catch (...) {
         return set_error(LENIA_ERR_STATE, "exception in lenia_backward");
     }

@@ -500,7 +500,7 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         uint16_t* host = split(*mm.m);
         const size_t bytes = 2 * mm.m->size() * sizeof(uint16_t);
         void* d = nullptr;
-        if (hipMalloc(&d, bytes) != hipSuccess)
+        if (device_alloc(&d, bytes) != hipSuccess)
             return set_error(LENIA_ERR_OUT_OF_MEMORY, "DFT tables");
         p->allocations.push_back(d);
         p->ws_bytes += bytes;
@@ -510,14 +510,14 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
     }
     const size_t kbytes = (size_t)w.NK * DT * DT * sizeof(float);
     void* d = nullptr;
-    if (hipMalloc(&d, kbytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "spectra");
+    if (device_alloc(&d, kbytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "spectra");
     p->allocations.push_back(d);
     p->ws_bytes += kbytes;
     w.dft_khat = (float*)d;
     hipError_t e = hipMemcpyAsync(d, kh, kbytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "uploading spectra");
     const size_t ubytes = (size_t)w.NK * w.cells() * sizeof(float);
-    if (hipMalloc(&d, ubytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "potentials");
+    if (device_alloc(&d, ubytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "potentials");
     p->allocations.push_back(d);
     p->ws_bytes += ubytes;
     w.dft_u = (float*)d;

@@ -199,9 +199,17 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
         }
         hipStream_t s = (hipStream_t)stream;
         const size_t cells = w.cells();
+        {
+            const size_t ab = w.a_elems() * sizeof(float), pb = w.p_elems() * sizeof(float);
+            const DebugBuf db[] = {{A_in, ab, "A_in", true}, {P_in, pb, "P_in", true},
+                                   {A_out, ab, "A_out", false}, {P_out, pb, "P_out", false},
+                                   {evo->walls, cells, "walls", false}};
+            lenia_status dst = debug_checks(p, db, 5, s);
+            if (dst != LENIA_OK) return dst;
+        }
         if (!p->evo_flags) {
             void* q = nullptr;
-            if (hipMalloc(&q, 3 * cells) != hipSuccess)
+            if (device_alloc(&q, 3 * cells) != hipSuccess)
                 return set_error(LENIA_ERR_OUT_OF_MEMORY, "operator workspace");
             p->allocations.push_back(q);
             p->ws_bytes += 3 * cells;
@@ -236,7 +244,7 @@ extern "C" lenia_status lenia_step_evolve(lenia_plan_t p, float* A_in, float* P_
         if (zero_flags) {
             if (!w.p_zero) {
                 void* q = nullptr;
-                if (hipMalloc(&q, 2 * (size_t)a.n_tiles) != hipSuccess)
+                if (device_alloc(&q, 2 * (size_t)a.n_tiles) != hipSuccess)
                     return set_error(LENIA_ERR_OUT_OF_MEMORY, "tile flags");
                 p->allocations.push_back(q);
                 p->ws_bytes += 2 * (size_t)a.n_tiles;

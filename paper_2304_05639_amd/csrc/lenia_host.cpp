@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +22,11 @@ using namespace lenia;
 namespace {
 
 thread_local std::string g_last_error;
+
+// Allocation-failure test hook (lenia_debug_fail_alloc): the number of device
+// allocations still let through before the failing ones, and how many fail.
+std::mutex g_fail_mu;
+int g_fail_skip = 0, g_fail_count = 0;
 
 lenia_status fail(lenia_status s, const std::string& msg)
 {
@@ -37,6 +43,28 @@ lenia_status set_error(lenia_status s, const std::string& msg) { return fail(s, 
 lenia_status hip_fail(hipError_t e, const char* what)
 {
     return fail(LENIA_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hipError_t device_alloc(void** ptr, size_t bytes)
+{
+    *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_fail_mu);
+        if (g_fail_count > 0) {
+            if (g_fail_skip > 0) {
+                --g_fail_skip;
+            } else {
+                --g_fail_count;
+                return hipErrorOutOfMemory;
+            }
+        }
+    }
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *ptr = nullptr;
+    }
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -174,7 +202,8 @@ lenia_status validate(const lenia_desc* d)
         return fail(LENIA_ERR_INVALID_ARG, "unknown conv form");
     if ((d->tile_y == 0) != (d->tile_x == 0) || d->tile_y < 0 || d->tile_x < 0)
         return fail(LENIA_ERR_INVALID_ARG, "tile_y and tile_x must both be 0 or both > 0");
-    if (d->flags & ~LENIA_FLAG_AUTOTUNE) return fail(LENIA_ERR_INVALID_ARG, "unknown flags");
+    if (d->flags & ~(LENIA_FLAG_AUTOTUNE | LENIA_FLAG_CHECK_FINITE))
+        return fail(LENIA_ERR_INVALID_ARG, "unknown flags");
     if (rings && !(d->localized && d->genotype_update))
         return fail(LENIA_ERR_INVALID_ARG, "ring-decomposed kernels need localized genes with "
                                            "genotype_update");
@@ -239,11 +268,19 @@ const char* lenia_status_str(lenia_status s)
     case LENIA_ERR_OUT_OF_MEMORY: return "LENIA_ERR_OUT_OF_MEMORY";
     case LENIA_ERR_HIP: return "LENIA_ERR_HIP";
     case LENIA_ERR_STATE: return "LENIA_ERR_STATE";
+    case LENIA_ERR_NONFINITE: return "LENIA_ERR_NONFINITE";
     }
     return "LENIA_ERR_UNKNOWN";
 }
 
 const char* lenia_last_error(void) { return g_last_error.c_str(); }
+
+void lenia_debug_fail_alloc(int32_t after, int32_t count)
+{
+    std::lock_guard<std::mutex> lock(g_fail_mu);
+    g_fail_skip = after > 0 ? after : 0;
+    g_fail_count = count > 0 ? count : 0;
+}
 
 lenia_status lenia_desc_validate(const lenia_desc* d)
 {

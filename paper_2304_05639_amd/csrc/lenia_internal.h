@@ -139,6 +139,12 @@ batch_launch_fn find_batch_launcher(int table, int R, int ty, int tx);
 int step_tile_candidates(int table, int R, int* ty, int* tx, int max);
 hipError_t launch_fill_synthetic(float* A, size_t nA, float* P, size_t plane, int nk,
                                  hipStream_t s);
+// hipMalloc through the library's allocation-failure test hook; *ptr is null
+// on failure
+hipError_t device_alloc(void** ptr, size_t bytes);
+// *flag |= bit if x[0, n) holds a NaN or an infinity
+hipError_t launch_find_nonfinite(const float* x, size_t n, uint32_t* flag, uint32_t bit,
+                                 hipStream_t s);
 // p[0, n) = 0 (a kernel, so that the call can sit in a captured graph)
 hipError_t launch_clear_bytes(uint8_t* p, uint32_t n, hipStream_t s);
 

@@ -59,16 +59,51 @@ static lenia_status dmalloc(lenia_plan_t p, void** ptr, size_t bytes)
 {
     *ptr = nullptr;
     if (bytes == 0) return LENIA_OK;
-    hipError_t e = hipMalloc(ptr, bytes);
+    hipError_t e = device_alloc(ptr, bytes);
     if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *ptr = nullptr;
         return set_error(LENIA_ERR_OUT_OF_MEMORY,
-                         "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                         "device allocation of " + std::to_string(bytes) + " bytes failed: " +
                              hipGetErrorString(e));
     }
     p->allocations.push_back(*ptr);
     p->ws_bytes += bytes;
+    return LENIA_OK;
+}
+
+lenia_status debug_checks(lenia_plan_t p, const DebugBuf* bufs, int n, hipStream_t s)
+{
+    if (!p->check_finite) return LENIA_OK;
+    for (int i = 0; i < n; ++i) {
+        if (!bufs[i].ptr || !bufs[i].bytes) continue;
+        hipDeviceptr_t base = nullptr;
+        size_t size = 0;
+        hipError_t e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)bufs[i].ptr);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(LENIA_ERR_INVALID_ARG,
+                             std::string(bufs[i].name) + " is not in a device allocation");
+        }
+        const size_t left = (size_t)((const char*)base + size - (const char*)bufs[i].ptr);
+        if (bufs[i].bytes > left)
+            return set_error(LENIA_ERR_INVALID_ARG,
+                             std::string(bufs[i].name) + " needs " + std::to_string(bufs[i].bytes) +
+                                 " bytes, its allocation holds " + std::to_string(left) +
+                                 " from there");
+    }
+    hipError_t e = launch_clear_bytes((uint8_t*)p->d_nonfinite, sizeof(uint32_t), s);
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        if (bufs[i].ptr && bufs[i].scan)
+            e = launch_find_nonfinite((const float*)bufs[i].ptr, bufs[i].bytes / sizeof(float),
+                                      p->d_nonfinite, 1u << i, s);
+    uint32_t found = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&found, p->d_nonfinite, sizeof(found), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "finite check");
+    for (int i = 0; i < n; ++i)
+        if (found & (1u << i))
+            return set_error(LENIA_ERR_NONFINITE,
+                             std::string("non-finite value in ") + bufs[i].name);
     return LENIA_OK;
 }
 
@@ -305,9 +340,9 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < p->worlds.size() && st == LENIA_OK; ++i) {
         WorldPlan& w = p->worlds[i];
-        if ((e = hipMalloc((void**)&outA[i], w.a_elems() * sizeof(float))) != hipSuccess) break;
+        if ((e = device_alloc((void**)&outA[i], w.a_elems() * sizeof(float))) != hipSuccess) break;
         if (w.mode == MODE_LOCAL_UPDATE &&
-            (e = hipMalloc((void**)&outP[i], w.p_elems() * sizeof(float))) != hipSuccess)
+            (e = device_alloc((void**)&outP[i], w.p_elems() * sizeof(float))) != hipSuccess)
             break;
         if ((e = launch_fill_synthetic(w.ws_A, w.a_elems(), w.mode == MODE_GLOBAL ? nullptr : w.ws_P,
                                        w.cells(), w.NK, s)) != hipSuccess)
@@ -351,8 +386,8 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
                     }
                     WorldArgs* dtab = nullptr;
                     int2* ditems = nullptr;
-                    e = hipMalloc((void**)&dtab, tab.size() * sizeof(WorldArgs));
-                    if (e == hipSuccess) e = hipMalloc((void**)&ditems, items.size() * sizeof(int2));
+                    e = device_alloc((void**)&dtab, tab.size() * sizeof(WorldArgs));
+                    if (e == hipSuccess) e = device_alloc((void**)&ditems, items.size() * sizeof(int2));
                     if (e == hipSuccess)
                         e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(WorldArgs), hipMemcpyHostToDevice);
                     if (e == hipSuccess)
@@ -470,11 +505,15 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     for (int i = 0; i < n && st == LENIA_OK; ++i) st = build_world(p, &ds[i], p->worlds[i], s, keep);
     if (st == LENIA_OK && conv_is_dft(p->conv))
         st = build_dft_tables(p, p->worlds[0], s, keep);
+    for (int i = 0; i < n; ++i)
+        if (ds[i].flags & LENIA_FLAG_CHECK_FINITE) p->check_finite = true;
+    if (st == LENIA_OK && p->check_finite)
+        st = dmalloc(p, (void**)&p->d_nonfinite, sizeof(uint32_t));
     if (st == LENIA_OK && batched) {
         for (int ph = 0; ph < 2 && st == LENIA_OK; ++ph) {
             void* q = nullptr;
             st = [&] {
-                hipError_t e = hipMalloc(&q, n * sizeof(WorldArgs));
+                hipError_t e = device_alloc(&q, n * sizeof(WorldArgs));
                 if (e != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "world table");
                 p->allocations.push_back(q);
                 p->d_tables[ph] = (WorldArgs*)q;
@@ -492,7 +531,7 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
         }
         p->n_items = (int)items.size();
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, items.size() * sizeof(int2));
+        hipError_t e = device_alloc(&q, items.size() * sizeof(int2));
         if (e != hipSuccess) {
             st = set_error(LENIA_ERR_OUT_OF_MEMORY, "work list");
         } else {
@@ -610,6 +649,16 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
                              "A and P must both be in place or both out of place");
         hipStream_t s = (hipStream_t)stream;
         const size_t abytes = w.a_elems() * sizeof(float), pbytes = w.p_elems() * sizeof(float);
+        {
+            const bool loc = (w.mode != MODE_GLOBAL);
+            const DebugBuf db[] = {{A_in, abytes, "A_in", true},
+                                   {loc ? P_in : nullptr, pbytes, "P_in", true},
+                                   {A_out, abytes, "A_out", false},
+                                   {upd ? P_out : nullptr, pbytes, "P_out", false},
+                                   {saved, saved ? lenia_saved_bytes(p) : 0, "saved", false}};
+            lenia_status dst = debug_checks(p, db, 5, s);
+            if (dst != LENIA_OK) return dst;
+        }
         if (n_steps == 0) {
             hipError_t e = hipSuccess;
             if (A_out != A_in) e = hipMemcpyAsync(A_out, A_in, abytes, hipMemcpyDeviceToDevice, s);
@@ -703,6 +752,12 @@ lenia_status lenia_potentials(lenia_plan_t p, const float* A, float* U, void* st
             return set_error(LENIA_ERR_INVALID_ARG, "U must not alias A");
         WorldPlan& w = p->worlds[0];
         hipStream_t s = (hipStream_t)stream;
+        {
+            const DebugBuf db[] = {{A, w.a_elems() * sizeof(float), "A", true},
+                                   {U, (size_t)w.NK * w.cells() * sizeof(float), "U", false}};
+            lenia_status dst = debug_checks(p, db, 2, s);
+            if (dst != LENIA_OK) return dst;
+        }
         hipError_t e;
         if (conv_is_dft(p->conv)) {
             e = launch_dft_potentials(p, w, A, U, s);
@@ -798,8 +853,16 @@ lenia_status lenia_step_batched(lenia_plan_t p, float* const* A, float* const* P
             if (p->mode != MODE_GLOBAL && (!P[i] || ((uintptr_t)P[i] & 3)))
                 return set_error(LENIA_ERR_INVALID_ARG, "P[" + std::to_string(i) + "] NULL or misaligned");
         }
-        if (n_steps == 0) return LENIA_OK;
         hipStream_t s = (hipStream_t)stream;
+        for (int i = 0; i < n && p->check_finite; ++i) {
+            const WorldPlan& w = p->worlds[i];
+            const std::string na = "A[" + std::to_string(i) + "]", np = "P[" + std::to_string(i) + "]";
+            const DebugBuf db[] = {{A[i], w.a_elems() * sizeof(float), na.c_str(), true},
+                                   {P ? P[i] : nullptr, w.p_elems() * sizeof(float), np.c_str(), true}};
+            lenia_status dst = debug_checks(p, db, 2, s);
+            if (dst != LENIA_OK) return dst;
+        }
+        if (n_steps == 0) return LENIA_OK;
         std::vector<float*> va(A, A + n), vp(n, nullptr);
         if (P) vp.assign(P, P + n);
         hipError_t e = hipSuccess;

@@ -67,6 +67,19 @@ struct BackwardWs {
     int n_part = 0;
 };
 
+// LENIA_FLAG_CHECK_FINITE: one caller buffer of a call.  Every buffer must lie
+// inside the device allocation that holds it; those with `scan` set must hold
+// finite floats only.
+struct DebugBuf {
+    const void* ptr;       // may be NULL (skipped)
+    size_t bytes;
+    const char* name;
+    bool scan;             // input buffer of floats: checked for NaN / infinity
+};
+// No-op unless the plan was made with LENIA_FLAG_CHECK_FINITE; otherwise the
+// checks above (the scan waits for the stream).
+lenia_status debug_checks(lenia_plan_t p, const DebugBuf* bufs, int n, hipStream_t s);
+
 typedef hipError_t (*epilogue_launch_fn)(const WorldArgs& w, const float* U, int mode,
                                          hipStream_t s);
 epilogue_launch_fn find_epilogue_launcher(int table);
@@ -99,5 +112,8 @@ struct lenia_plan_ {
     uint8_t* evo_flags = nullptr;
     uint8_t* evo_eoxy = nullptr;
     uint8_t* evo_epen = nullptr;
+    // LENIA_FLAG_CHECK_FINITE: one bit per scanned buffer of a call
+    bool check_finite = false;
+    uint32_t* d_nonfinite = nullptr;
     std::vector<void*> allocations;
 };

@@ -15,6 +15,7 @@
 //      applies the localized growth (Section 2.4) and the clipped dt update,
 //      and writes A', P' (and, on request, u_k and alpha for the adjoint).
 // Output goes to buffers distinct from the inputs (the host ping-pongs).
+#include <algorithm>
 #include <utility>
 
 #include "lenia_device.h"
@@ -874,6 +875,25 @@ hipError_t launch_clear_bytes(uint8_t* p, uint32_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(fill_bytes_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void find_nonfinite_kernel(const float* __restrict__ x, size_t n,
+                                                            uint32_t* flag, uint32_t bit)
+{
+    const size_t stride = (size_t)gridDim.x * 256;
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+        bad |= !isfinite(x[i]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, bit);
+}
+
+hipError_t launch_find_nonfinite(const float* x, size_t n, uint32_t* flag, uint32_t bit,
+                                 hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(find_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag, bit);
     return hipGetLastError();
 }
 

@@ -16,14 +16,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblenia.so")
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_STATE = range(6)
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_STATE, ERR_NONFINITE = range(7)
 CONV_AUTO, CONV_DIRECT_F32, CONV_DFT_SPLIT_BF16, CONV_DFT_SPLIT_F16 = range(4)
 FLAG_AUTOTUNE = 1
+FLAG_CHECK_FINITE = 2
 
 API = ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan", "lenia_plan_batched",
        "lenia_step", "lenia_step_batched", "lenia_potentials", "lenia_saved_bytes", "lenia_backward",
        "lenia_step_evolve", "lenia_plan_get_info", "lenia_plan_destroy", "lenia_status_str",
-       "lenia_last_error")
+       "lenia_last_error", "lenia_debug_fail_alloc")
 
 
 class LeniaError(RuntimeError):
@@ -94,6 +95,8 @@ def lib():
         L.lenia_status_str.argtypes = [C.c_int]
         L.lenia_status_str.restype = C.c_char_p
         L.lenia_last_error.restype = C.c_char_p
+        L.lenia_debug_fail_alloc.argtypes = [C.c_int32, C.c_int32]
+        L.lenia_debug_fail_alloc.restype = None
         for name in ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan",
                      "lenia_plan_batched", "lenia_step", "lenia_step_batched",
                      "lenia_potentials", "lenia_backward", "lenia_plan_get_info",
@@ -101,6 +104,12 @@ def lib():
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
+
+
+def debug_fail_alloc(after: int, count: int) -> None:
+    """Test hook: let `after` device allocations of the library through, then
+    fail `count` of them (count <= 0: off)."""
+    lib().lenia_debug_fail_alloc(int(after), int(count))
 
 
 def _status_name(s: int) -> str:
@@ -120,7 +129,7 @@ class DescBuilder:
     lenia_desc and keeps the host arrays alive."""
 
     def __init__(self, w, conv: int = CONV_AUTO, tile: Optional[Sequence[int]] = None,
-                 autotune: bool = False):
+                 autotune: bool = False, check_finite: bool = False):
         nk = int(w.n_kernels)
         self._src = np.ascontiguousarray(w.src, np.int32)
         self._dst = np.ascontiguousarray(w.dst, np.int32)
@@ -137,7 +146,8 @@ class DescBuilder:
                          int(w.R), ip(self._nsh), dp(self._beta), float(w.dt), int(w.localized),
                          int(w.genotype_update), dp(self._m), dp(self._s), dp(self._h),
                          float(w.eps), int(w.r_diff), int(conv), int(ty), int(tx),
-                         FLAG_AUTOTUNE if autotune else 0, int(getattr(w, "n_ring", 0)))
+                         (FLAG_AUTOTUNE if autotune else 0) |
+                         (FLAG_CHECK_FINITE if check_finite else 0), int(getattr(w, "n_ring", 0)))
 
 
 def validate(w, **kw) -> int:
@@ -184,9 +194,9 @@ class Plan:
     """A single-world plan (lenia_plan)."""
 
     def __init__(self, world, conv: int = CONV_AUTO, tile=None, autotune: bool = False,
-                 stream=None):
+                 stream=None, check_finite: bool = False):
         self.world = world
-        self._b = DescBuilder(world, conv, tile, autotune)
+        self._b = DescBuilder(world, conv, tile, autotune, check_finite)
         h = C.c_void_p()
         _check(lib().lenia_plan(C.byref(self._b.desc), C.c_void_p(_stream(stream)), C.byref(h)),
                "lenia_plan")

@@ -101,8 +101,21 @@ def test_unknown_tile_and_flags():
 
 def test_status_strings():
     lib = L.lib()
-    for code, name in [(0, b"LENIA_OK"), (1, b"LENIA_ERR_INVALID_ARG"), (4, b"LENIA_ERR_HIP")]:
+    for code, name in [(0, b"LENIA_OK"), (1, b"LENIA_ERR_INVALID_ARG"), (4, b"LENIA_ERR_HIP"),
+                       (6, b"LENIA_ERR_NONFINITE")]:
         assert lib.lenia_status_str(code) == name
+
+
+def test_check_finite_flag_validates():
+    import ctypes
+    w = inputs.test_world(32, 32, seed=2, n_blobs=1)
+    b = L.DescBuilder(w, check_finite=True)
+    assert b.desc.flags == L.FLAG_CHECK_FINITE
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
+    b.desc.flags = L.FLAG_CHECK_FINITE | L.FLAG_AUTOTUNE
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
+    b.desc.flags = L.FLAG_CHECK_FINITE | 4
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.ERR_INVALID_ARG
 
 
 def test_null_descriptor_rejected():

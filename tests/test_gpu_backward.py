@@ -337,3 +337,33 @@ def test_c5_gradient_error_report(L, oracle):
         print(f"C5 gradients conv={conv}: rel L2 " +
               " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
         assert all(np.isfinite(v) for v in errs.values())
+
+
+def test_backward_allocation_failure_then_retry(L):
+    """The adjoint's three workspaces are allocated on the first call, all or
+    none: when the first, second or third allocation fails the call returns
+    out-of-memory and leaves the plan as it was, and the next call allocates
+    again and gives the same bits as a plan whose first call succeeded."""
+    import torch
+    w = inputs.test_world(64, 64, seed=231, n_blobs=6)
+    rng = np.random.default_rng(231)
+    gA1 = rng.standard_normal(w.A.shape).astype(np.float32)
+    gP1 = rng.standard_normal(w.P.shape).astype(np.float32)
+    ref = _gpu_vjp(L, w, gA1, gP1)
+    plan = L.Plan(w)
+    A, P = dev(w.A), dev(w.P)
+    saved = plan.new_saved()
+    plan.step(A, P, saved=saved)
+    torch.cuda.synchronize()
+    for after in (0, 1, 2):
+        L.debug_fail_alloc(after, 1)
+        try:
+            with pytest.raises(L.LeniaError) as e:
+                plan.backward(A, P, saved, dev(gA1), dev(gP1))
+            assert e.value.status == L.ERR_OUT_OF_MEMORY
+        finally:
+            L.debug_fail_alloc(0, 0)
+    gA, gP, gb = plan.backward(A, P, saved, dev(gA1), dev(gP1))
+    torch.cuda.synchronize()
+    for a, b in zip((host(gA), host(gP), host(gb)), ref):
+        assert np.array_equal(a, b)

@@ -277,3 +277,41 @@ def test_full_size_sampled_windows(L, oracle, c3_world, t0):
                      max_excluded=MAX_EXCLUDED_WINDOW)
     print(f"4096^2 at t={t0}: {len(starts)} windows, {active} cells with alpha = 1")
     assert active > 0
+
+
+def test_check_finite_flag(L):
+    """LENIA_FLAG_CHECK_FINITE: a plan with the flag steps exactly like one
+    without it; a NaN or an infinity in an input buffer returns
+    LENIA_ERR_NONFINITE before anything is enqueued (the outputs keep their
+    contents)."""
+    import torch
+    w = inputs.test_world(64, 80, seed=121, n_blobs=4)
+    ref = gpu_step(L.Plan(w), w.A, w.P)
+    plan = L.Plan(w, check_finite=True)
+    got = gpu_step(plan, w.A, w.P)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    for which, val in (("A", np.nan), ("A", np.inf), ("P", -np.inf), ("P", np.nan)):
+        A, P = w.A.copy(), w.P.copy()
+        (A if which == "A" else P).reshape(-1)[777] = val
+        A_out = torch.full(w.A.shape, 7.0, device="cuda")
+        P_out = torch.full(w.P.shape, 7.0, device="cuda")
+        with pytest.raises(L.LeniaError) as e:
+            plan.step(dev(A), dev(P), A_out, P_out)
+        torch.cuda.synchronize()
+        assert e.value.status == L.ERR_NONFINITE, str(e.value)
+        assert (host(A_out) == 7.0).all() and (host(P_out) == 7.0).all()
+    A = w.A.copy()
+    A[1, 5, 6] = np.nan
+    with pytest.raises(L.LeniaError) as e:
+        plan.potentials(dev(A))
+    assert e.value.status == L.ERR_NONFINITE
+    # the adjoint checks its cotangents too
+    saved = plan.new_saved()
+    At, Pt = dev(w.A), dev(w.P)
+    plan.step(At, Pt, saved=saved)
+    gA1 = np.zeros(w.A.shape, np.float32)
+    gA1[2, 3, 4] = np.inf
+    with pytest.raises(L.LeniaError) as e:
+        plan.backward(At, Pt, saved, dev(gA1), dev(np.zeros(w.P.shape, np.float32)))
+    assert e.value.status == L.ERR_NONFINITE
+    torch.cuda.synchronize()
