@@ -14,10 +14,18 @@
 // where C_V / S_V keep the V output rows (columns) of the inverse transform.
 // Every GEMM runs on v_mfma_f32_16x16x32_bf16 (or _f16) with FP32
 // accumulation; each operand x is split as hi = e(x), lo = e(x - hi) in the
-// operand type e and a product is hi*hi + hi*lo + lo*hi (about 16 significant
-// bits with bf16, about 22 with fp16 for operands of magnitude above 2^-3).
-// The DFT matrices are built in FP64 on the host and split there; data
-// operands are split here.
+// operand type e and a product is hi*hi + hi*lo + lo*hi: about 16 significant
+// bits with bf16 and 22 with fp16.  fp16 keeps those 22 bits only while lo
+// stays a normal number, |x| >= 2^-3, so every operand is scaled by a power
+// of two that puts its largest possible magnitude just below 2^14 (far from
+// fp16's largest value, 65504): the DFT matrices (|x| <= 1) by 2^14 on the
+// host, the window by 2^a from its largest magnitude, and each intermediate
+// by the bound its GEMM implies (a K-term sum of products below 2^28).  An
+// element then loses precision only below 2^-17 of that bound, where its
+// absolute error (half of fp16's subnormal step) is 2^-39 of it.  The scales
+// are exact, so they cancel in the result and leave the bf16 form's rounding
+// unchanged.  The DFT matrices are built in FP64 on the host and split there;
+// data operands are split here.
 //
 // MFMA operand layouts (16x16x32): lane l holds A[l % 16][8 (l / 16) + j] and
 // B[8 (l / 16) + j][l % 16] for j < 8; the 16 x 16 FP32 result has
@@ -60,6 +68,18 @@ struct Op<_Float16> {
     }
 };
 
+// Power-of-two scales of the operands (see the header): the DFT matrices
+// carry 2^14; GEMM1's output (64 terms below 2^28) is split at 2^-20, the
+// spectral product (the transformed channel, 128 terms below 2^28, times a
+// spectrum of magnitude <= 2^-12) at 2^-9, folded into the spectra, and
+// GEMM3's output (128 terms) at 2^-21.  With the window scaled by 2^a the
+// potentials come out scaled by 2^(a + 6).
+constexpr int kMatExp = 14;
+constexpr int kYExp = -20;
+constexpr int kUExp = -9;
+constexpr int kZExp = -21;
+constexpr int kOutExp = 6;
+
 constexpr int DT = 64;                   // DFT tile
 constexpr int DT2 = 128;                 // real-embedded complex dimension
 constexpr int XS_P = DT + 8;             // LDS row pitches (bf16 / fp32 elements)
@@ -74,7 +94,7 @@ struct DftTables {
     const void* f2;       // [2][128][128] hi, lo of [[C, S], [-S, C]]
     const void* f3;       // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
     const void* f4t;      // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
-    const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2
+    const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2, times 2^kUExp
 };
 
 struct DftArgs {
@@ -107,6 +127,13 @@ __device__ __forceinline__ void split8(const float (&x)[8], typename Op<E>::v8& 
 
 template <class E>
 __device__ __forceinline__ typename Op<E>::v8 ld8(const E* p) { return *(const typename Op<E>::v8*)p; }
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
 
 // Writes 4 consecutive values (split) as hi / lo.
 template <class E>
@@ -141,6 +168,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     constexpr int SCRATCH_E = (FWD_E > INV_E) ? FWD_E : INV_E;
     __shared__ float xh[XH_FLOATS];
     __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
+    __shared__ float wmax[4];
     E* xs_hi = scr;
     E* xs_lo = scr + DT * XS_P;
     E* yt_hi = scr + 2 * DT * XS_P;
@@ -191,17 +219,37 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     // ---- per source channel: forward transform, then its kernels ------------
     for (int s = 0; s < T::C; ++s) {
         __syncthreads();
-        // stage the 64 x 64 window (wrapped) as bf16 hi / lo
-        for (int i = threadIdx.x; i < DT * DT / 4; i += 256) {
+        // load the 64 x 64 window (wrapped) and its largest magnitude, then
+        // stage it scaled by 2^a (largest magnitude below 2^14) as hi / lo
+        constexpr int NWIN = DT * DT / 4 / 256;
+        f32x4 win[NWIN];
+        float vmax = 0.f;
+#pragma unroll
+        for (int it = 0; it < NWIN; ++it) {
+            const int i = threadIdx.x + 256 * it;
             const int r = i / (DT / 4), c4 = (i % (DT / 4)) * 4;
-            f32x4 v;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 int gy = y0 - R + r, gx = x0 - R + c4 + j;
                 wrap2(gy, gx, H, W, single_wrap);
-                v[j] = g.A[(size_t)s * HW + (size_t)gy * W + gx];
+                win[it][j] = g.A[(size_t)s * HW + (size_t)gy * W + gx];
+                vmax = fmaxf(vmax, fabsf(win[it][j]));
             }
-            st4_split<E>(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, v);
+        }
+        vmax = wave_max(vmax);
+        if (lane == 0) wmax[wave] = vmax;
+        __syncthreads();
+        vmax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        int ea = 0;
+        (void)frexpf(vmax, &ea);                        // vmax < 2^ea
+        const int a = (vmax > 0.f) ? min(max(14 - ea, -100), 100) : 0;
+        const float sx = ldexpf(1.f, a);
+        const float sout = ldexpf(1.f, -(a + kOutExp));
+#pragma unroll
+        for (int it = 0; it < NWIN; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            const int r = i / (DT / 4), c4 = (i % (DT / 4)) * 4;
+            st4_split<E>(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, win[it] * sx);
         }
         __syncthreads();
         // GEMM1: wave w computes rows 16w..16w+15 of Y, all 8 column blocks
@@ -227,7 +275,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
             for (int n = 0; n < 8; ++n) {
                 const int c = 16 * n + lr;
                 const int off = (c % DT) * YT_P + DT * (c / DT) + 16 * wave + ld;
-                st4_split<E>(yt_hi + off, yt_lo + off, acc[n]);
+                st4_split<E>(yt_hi + off, yt_lo + off, acc[n] * ldexpf(1.f, kYExp));
             }
         }
         __syncthreads();
@@ -322,7 +370,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                         // column block 4 holds row block `wave` only, in acc[1][0]
                         const int mm = (q == 0) ? m : wave;
                         const int off = p * ZC_P + col0 + 16 * mm + ld;
-                        st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m]);
+                        st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m] * ldexpf(1.f, kZExp));
                     }
                 }
             }
@@ -353,7 +401,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const int p = 16 * m + ld + j, gy = y0 + p;
-                            if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j];
+                            if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j] * sout;
                         }
                 }
             }
@@ -448,7 +496,9 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         }
     // hi = round(x), lo = round(x - hi) in the operand type of the plan's form
     const bool f16 = (p->conv == LENIA_CONV_DFT_SPLIT_F16);
-    auto split = [&](const std::vector<double>& m) {
+    auto split = [&](const std::vector<double>& mu) {
+        std::vector<double> m(mu.size());
+        for (size_t i = 0; i < m.size(); ++i) m[i] = std::ldexp(mu[i], kMatExp);
         uint16_t* out = new uint16_t[2 * m.size()];
         for (size_t i = 0; i < m.size(); ++i) {
             if (f16) {
@@ -489,7 +539,7 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
             for (int f1 = 0; f1 < DT; ++f1) {
                 double acc = 0.0;
                 for (int y = 0; y < DT; ++y) acc += t1[y * DT + f2i] * C(f1, y);
-                kh[((size_t)k * DT + f2i) * DT + f1] = (float)(acc / (DT * DT));
+                kh[((size_t)k * DT + f2i) * DT + f1] = (float)std::ldexp(acc / (DT * DT), kUExp);
             }
     }
     const struct {

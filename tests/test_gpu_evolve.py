@@ -42,12 +42,12 @@ def _walls(H, W):
     return walls
 
 
-@pytest.mark.parametrize("conv,tol", [(1, TOL_STATE), (2, 5e-4)])
+@pytest.mark.parametrize("conv,tol", [(1, TOL_STATE), (2, 5e-4), (3, TOL_STATE)])
 def test_evolve_teacher_forced(L, oracle, conv, tol):
     import torch
     H, W, r_oxy = 96, 128, 4
     w = inputs.test_world(H, W, seed=801, n_blobs=24)
-    d = oracle.Desc.from_world(w, tau=1e-5 if conv == 1 else 2e-5)
+    d = oracle.Desc.from_world(w, tau=2e-5 if conv == 2 else 1e-5)
     plan = L.Plan(w, conv=conv)
     walls = _walls(H, W)
     wt = torch.tensor(walls, device="cuda")
