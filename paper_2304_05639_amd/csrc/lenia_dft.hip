@@ -41,6 +41,14 @@
 #include "lenia_internal.h"
 #include "lenia_plan.h"
 
+// No floating-point contraction in this file.  A split must take hi and lo
+// from one rounded value: with contraction the compiler may fuse the product
+// x = a * b into lo = e(a * b - hi) (an FMA on the exact product, v_fma_mix
+// for fp16) while hi is converted from the rounded product, and where the two
+// fall on either side of an fp16 rounding tie lo comes out one hi-ulp off
+// (2^-11 relative on that element).
+#pragma clang fp contract(off)
+
 namespace lenia {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
