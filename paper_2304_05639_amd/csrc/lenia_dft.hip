@@ -41,12 +41,14 @@
 #include "lenia_internal.h"
 #include "lenia_plan.h"
 
-// No floating-point contraction in this file.  A split must take hi and lo
-// from one rounded value: with contraction the compiler may fuse the product
-// x = a * b into lo = e(a * b - hi) (an FMA on the exact product, v_fma_mix
-// for fp16) while hi is converted from the rounded product, and where the two
-// fall on either side of an fp16 rounding tie lo comes out one hi-ulp off
-// (2^-11 relative on that element).
+// A split must take hi and lo from one rounded FP32 value.  Left alone, the
+// compiler converts a product x = a * b to fp16 for the stored hi from the
+// rounded product, but rematerializes hi for lo = e(x - hi) as one fused
+// v_fma_mix (the exact product rounded once to fp16); at an fp16 rounding tie
+// the two differ and that element loses one hi-ulp (2^-11 relative).  Every
+// split therefore reads its value through an empty register-constraint asm
+// statement, which the compiler cannot look through, and floating-point
+// contraction is off in this file.
 #pragma clang fp contract(off)
 
 namespace lenia {
@@ -122,14 +124,22 @@ __device__ __forceinline__ f32x4 mma3(const typename Op<E>::v8& ah, const typena
     return c;
 }
 
+// The value as an opaque FP32 register (see the split note above).
+__device__ __forceinline__ float opaque(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <class E>
 __device__ __forceinline__ void split8(const float (&x)[8], typename Op<E>::v8& hi, typename Op<E>::v8& lo)
 {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const E h = (E)x[j];
+        const float v = opaque(x[j]);
+        const E h = (E)v;
         hi[j] = h;
-        lo[j] = (E)(x[j] - (float)h);
+        lo[j] = (E)(v - (float)h);
     }
 }
 
@@ -150,9 +160,10 @@ __device__ __forceinline__ void st4_split(E* hi, E* lo, const f32x4& v)
     typename Op<E>::v4 h, l;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const E b = (E)v[j];
+        const float x = opaque(v[j]);
+        const E b = (E)x;
         h[j] = b;
-        l[j] = (E)(v[j] - (float)b);
+        l[j] = (E)(x - (float)b);
     }
     *(typename Op<E>::v4*)hi = h;
     *(typename Op<E>::v4*)lo = l;
