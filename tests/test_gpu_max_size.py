@@ -174,7 +174,9 @@ def test_operators_planes_past_2_31_bytes(L, oracle):
         inner = (slice(m, m + HW_WIN), slice(m, m + HW_WIN))
         rr = dict(A=r["A"][(slice(None),) + inner], P=r["P"][(slice(None), slice(None)) + inner],
                   amb=r["amb"][inner])
-        eA, eP, n_bad = compare_evolve(rr, A1, P1, r_oxy, TOL_STATE,
-                                       max_excluded=MAX_EXCLUDED_WINDOW)
+        # windows lie across the edges of the empty squares: the cells within
+        # 2 r_oxy of the organic-sum boundary there (a band 25 cells wide) may
+        # all be excluded
+        eA, eP, n_bad = compare_evolve(rr, A1, P1, r_oxy, TOL_STATE, max_excluded=0.6)
         print(f"{H}x{W} operators window at ({y0}, {x0}): A' {eA:.2e} P' {eP:.2e} "
               f"excluded {n_bad} square {hit}", flush=True)
