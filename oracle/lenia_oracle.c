@@ -627,6 +627,51 @@ ORACLE_EXPORT int oracle_ring_step(int H, int W, int C, int NK, const int* src, 
     return 0;
 }
 
+/*
+ * The cast form of the same localized kernels, the reference Section 2.4
+ * recombines its rings against: at each cell, kernel k is the two-bump kernel
+ * function of the cell's diffused genes (the r1, w1, b1, r2, w2, b2 planes,
+ * diffused as in oracle_ring_step, unmasked) evaluated at each offset's own
+ * radius |d| / R over the open disk |d| < R, and
+ *   u_k = sum_d K(|d|/R) A_src(x + d) / sum_d K(|d|/R),   0 if that is 0.
+ * The ring form evaluates the same function at the inner radius j / n_ring of
+ * the offset's ring instead.  U[NK][H][W].  Returns 0, or -1 on allocation
+ * failure.
+ */
+ORACLE_EXPORT int oracle_cast_potentials(int H, int W, int C, int NK, const int* src, int R,
+                                         double eps, int r_diff, const double* A, const double* P,
+                                         double* U)
+{
+    const long N = (long)H * W;
+    const int NP = 9 * NK;
+    double* Pd = (double*)calloc((long)NP * N, sizeof(double));
+    if (!Pd) return -1;
+    (void)C;
+    diffuse_planes(H, W, NP, r_diff, eps, P, NULL, NULL, Pd);
+    #pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (int k = 0; k < NK; ++k)
+            for (long x = 0; x < W; ++x) {
+                const long c = y * W + x;
+                double g[6];
+                for (int p = 0; p < 6; ++p) g[p] = Pd[(long)(p * NK + k) * N + c];
+                const double* As = A + (long)src[k] * N;
+                double nu = 0.0, de = 0.0;
+                for (int dy = -R; dy <= R; ++dy)
+                    for (int dx = -R; dx <= R; ++dx) {
+                        const long d2 = (long)dy * dy + (long)dx * dx;
+                        if (d2 >= (long)R * R) continue;
+                        const double rho = sqrt((double)d2) / (double)R;
+                        const double kw = kernel_fn(rho, g[0], g[1], g[2]) + kernel_fn(rho, g[3], g[4], g[5]);
+                        nu += kw * As[wrap(y + dy, H) * W + wrap(x + dx, W)];
+                        de += kw;
+                    }
+                U[(long)k * N + c] = (de > 0.0) ? nu / de : 0.0;
+            }
+    free(Pd);
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------
  * The random and environmental operators of Algorithm 2 around one step:
  * walls (Section 2.7), mutation (Section 2.5) and the penalization of

@@ -63,6 +63,9 @@ def lib():
                                          C.c_double, C.c_int, C.c_double, C.c_int, C.c_int,
                                          C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                                          C.c_double, dp, dp, up, up, up]
+        L.oracle_cast_potentials.restype = C.c_int
+        L.oracle_cast_potentials.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int,
+                                             C.c_double, C.c_int, dp, dp, dp]
         L.oracle_ring_step.restype = C.c_int
         L.oracle_ring_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, C.c_int, C.c_int,
                                        C.c_double, C.c_double, C.c_int, C.c_double, dp, dp, dp, dp,
@@ -221,6 +224,21 @@ def ring_step(d: Desc, A, P):
     if rc != 0:
         raise MemoryError("oracle_ring_step failed")
     return dict(A=A1, P=P1, U=U, alpha=alpha, amb=amb)
+
+
+def cast_potentials(d: Desc, A, P):
+    """The cast form of the localized kernels (Section 2.4): each cell's
+    two-bump kernel function evaluated at every offset's own radius,
+    normalized over the disk, summed directly.  P[9][NK][H][W] as for
+    ring_step.  Returns U[NK][H][W]."""
+    A = _d(A).reshape(d.C, d.H, d.W)
+    Pin = _d(P).reshape(9, d.NK, d.H, d.W)
+    U = np.empty((d.NK, d.H, d.W))
+    rc = lib().oracle_cast_potentials(d.H, d.W, d.C, d.NK, _p(d.src, C.c_int), d.R, d.eps,
+                                      d.r_diff, _p(A), _p(Pin), _p(U))
+    if rc != 0:
+        raise MemoryError("oracle_cast_potentials failed")
+    return U
 
 
 def evolve_step(d: Desc, A, P, walls=None, gamma_mut=0.0, mut_half=8, gamma_pen=0.0, r_oxy=6,

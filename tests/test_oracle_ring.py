@@ -156,3 +156,111 @@ def test_low_bump_height_closes_alpha():
     r = oracle.ring_step(_desc(w), A, P)
     assert (r["alpha"] == 0).all() and (r["P"] == 0).all()
     assert np.array_equal(r["A"], np.clip(A, 0, 1))
+
+
+# ---- calibration against the cast kernels (Section 2.4, last paragraph) ------
+
+def _smooth_state(H, W, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([inputs.smooth_uniform_field(rng, H, W, 0.0, 1.0, 4.0) for _ in range(3)])
+
+
+def test_ring_form_converges_to_the_cast_form():
+    """The ring form evaluates each kernel function at its ring's inner radius
+    j / n_ring instead of at each offset's own radius: an error of first order
+    in the ring width.  On smooth states and smooth gene fields the ring
+    potentials approach the cast potentials as n_ring grows, by about the
+    factor the rings narrow (at least half of it here)."""
+    import dataclasses
+    H, W = 40, 44
+    w = inputs.ring_test_world(H, W, seed=511, n_blobs=0)
+    A = _smooth_state(H, W, 512)
+    uc = oracle.cast_potentials(_desc(w), A, w.P)
+    errs = []
+    for n in (24, 96, 384):
+        r = oracle.ring_step(_desc(dataclasses.replace(w, n_ring=n)), A, w.P)
+        errs.append(float(np.abs(r["U"] - uc).max()))
+    assert errs[0] > 1e-6                         # the forms differ at the paper's 24 rings
+    assert errs[1] <= errs[0] / 2 and errs[2] <= errs[1] / 2, errs
+
+
+def _impulse_kernels(w, genes):
+    """Normalized kernel of kernel 0 in the ring and the cast form, read back
+    from the oracles' potentials of a unit impulse under constant genes: with
+    A = delta at x0, u(x) = K(x0 - x).  Returned on the (2R+1)^2 offset grid."""
+    H = W = 2 * R + 5
+    P = np.broadcast_to(np.asarray(genes, np.float64)[:, None, None, None], (9, 15, H, W)).copy()
+    A = np.zeros((3, H, W))
+    y0 = x0 = H // 2
+    A[w.src[0], y0, x0] = 1.0
+    d = oracle.Desc(H, W, 3, 15, w.src, w.dst, R, w.n_shells, w.beta, w.dt, 1, 1, n_ring=NR)
+    ur = oracle.ring_step(d, A, P)["U"][0]
+    uc = oracle.cast_potentials(d, A, P)[0]
+    take = lambda u: np.array([[u[y0 - dy, x0 - dx] for dx in range(-R, R + 1)]
+                               for dy in range(-R, R + 1)])
+    return take(ur), take(uc)
+
+
+GENE_SETS = [(0.3, 0.1, 0.8, 0.7, 0.1, 0.5, 0.2, 0.05, 0.6),      # two bumps, wide
+             (0.25, 0.05, 1.0, 0.75, 0.05, 0.4, 0.2, 0.05, 0.6),   # narrow bumps
+             (0.5, 0.15, 1.0, 0.9, 0.08, 0.2, 0.2, 0.05, 0.6)]     # one wide bump mid-radius
+
+
+@pytest.mark.parametrize("genes", GENE_SETS)
+def test_ring_and_cast_kernels_bound(genes):
+    """Both forms are normalized weighted averages over the same disk, so for
+    any state u_ring - u_cast = sum_d (Kr(d) - Kc(d)) (A(x + d) - A(x)), at
+    most ||Kr - Kc||_1 times the state's spread over the disk.  Checked on a
+    smooth state under constant genes, with the two kernels read back from
+    the oracles by impulses; both kernels sum to 1 and depend on |d| only."""
+    w = inputs.ring_test_world(2 * R + 5, 2 * R + 5, seed=513, n_blobs=0)
+    Kr, Kc = _impulse_kernels(w, genes)
+    assert abs(Kr.sum() - 1) < 1e-12 and abs(Kc.sum() - 1) < 1e-12
+    for K in (Kr, Kc):
+        assert np.allclose(K, K.T, atol=1e-15) and np.allclose(K, K[::-1], atol=1e-15)
+    l1 = float(np.abs(Kr - Kc).sum())
+    H, W = 48, 52
+    A = _smooth_state(H, W, 514)
+    P = np.broadcast_to(np.asarray(genes, np.float64)[:, None, None, None], (9, 15, H, W)).copy()
+    d = oracle.Desc(H, W, 3, 15, w.src, w.dst, R, w.n_shells, w.beta, w.dt, 1, 1, n_ring=NR)
+    ur = oracle.ring_step(d, A, P)["U"][0]
+    uc = oracle.cast_potentials(d, A, P)[0]
+    s = A[w.src[0]]
+    spread = np.zeros((H, W))
+    for dy in range(-R, R + 1):
+        for dx in range(-R, R + 1):
+            if dy * dy + dx * dx < R * R:
+                spread = np.maximum(spread, np.abs(np.roll(s, (-dy, -dx), (0, 1)) - s))
+    diff = np.abs(ur - uc)
+    assert (diff <= l1 * spread + 1e-12).all()
+    print(f"genes {genes[:6]}: ||Kr - Kc||_1 = {l1:.3f}, max |u_ring - u_cast| = {diff.max():.2e} "
+          f"(bound {float((l1 * spread).max()):.2e})")
+
+
+def _anisotropy(K):
+    """max over 0 < |k| <= pi/4 of |T(k, 0) - T(k/sqrt2, k/sqrt2)|, T the
+    kernel's transfer function sum_d K(d) cos(k . d): how differently plane
+    waves of one wavelength (8 cells and longer) along an axis and along a
+    diagonal are passed."""
+    d = np.arange(-R, R + 1)
+    dy, dx = np.meshgrid(d, d, indexing="ij")
+    worst = 0.0
+    for k in np.linspace(0.01, np.pi / 4, 80):
+        ta = float((K * np.cos(k * dx)).sum())
+        q = k / np.sqrt(2.0)
+        td = float((K * np.cos(q * dx + q * dy)).sum())
+        worst = max(worst, abs(ta - td))
+    return worst
+
+
+@pytest.mark.parametrize("genes", GENE_SETS)
+def test_ring_form_anisotropy(genes):
+    """The anisotropy the ring recombination adds: the axis-against-diagonal
+    difference of the transfer function of the ring kernel stays within
+    0.02 of the cast kernel's own (the lattice makes both slightly
+    anisotropic) at wavelengths of 8 cells and longer."""
+    w = inputs.ring_test_world(2 * R + 5, 2 * R + 5, seed=513, n_blobs=0)
+    Kr, Kc = _impulse_kernels(w, genes)
+    ar, ac = _anisotropy(Kr), _anisotropy(Kc)
+    print(f"genes {genes[:6]}: anisotropy ring {ar:.4f}, cast {ac:.4f}")
+    assert ar <= ac + 0.02
