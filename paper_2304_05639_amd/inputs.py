@@ -342,3 +342,101 @@ def device_state(w: World, seed: int, block: int = 1024, device: str = "cuda"):
             P[pi, k].uniform_(lo, hi, generator=g)
     P[0, 0, :block, :] = 0.0
     return A, P
+
+
+# ---- the same recipes drawn on the device -------------------------------------
+#
+# The benchmark's batched and ring-form workloads hold billions of gene values,
+# which the numpy recipe above draws in minutes.  These functions follow the
+# same recipe on the device with torch's generator: shells from numpy
+# default_rng(seed) as in localized_world, then with a torch generator seeded
+# with `seed` the gene fields (i.i.d. N(0,1) in FP64, the circular Gaussian
+# blur in FP64 by FFT, divided by the empirical standard deviation, the normal
+# CDF, affinely to [lo, hi], rounded to float32; same order), blob corners
+# and values (later blobs overwrite earlier ones) and, with per_blob_genes,
+# the blobs' own genes.  The values differ from the numpy draws (another
+# generator); the distributions are the same.  These worlds are not compared
+# with the oracle.
+
+def _device_smooth_field(g, H: int, W: int, lo: float, hi: float, sigma: float, device):
+    import math
+    import torch
+    z = torch.randn((H, W), generator=g, device=device, dtype=torch.float64)
+    fy = torch.fft.fftfreq(H, device=device, dtype=torch.float64)[:, None]
+    fx = torch.fft.rfftfreq(W, device=device, dtype=torch.float64)[None, :]
+    tf = torch.exp(-2.0 * math.pi ** 2 * sigma ** 2 * (fy ** 2 + fx ** 2))
+    y = torch.fft.irfft2(torch.fft.rfft2(z) * tf, s=(H, W))
+    sd = float(y.std(correction=0))
+    if sd > 0:
+        y = y / sd
+    u = torch.special.ndtr(y)
+    return (lo + (hi - lo) * u).to(torch.float32)
+
+
+def device_world(H: int, W: int, n_blobs: int, seed: int, per_blob_genes: bool = False,
+                 ring: bool = False, R: int = 12, dt: float = 0.2, n_ring: int = 24,
+                 name: str = "", device: str = "cuda"):
+    """A localized_world (or, with ring=True, a ring_world) drawn on the device.
+    Returns (World with A = P = None, A, P) with A, P float32 device tensors."""
+    import torch
+    rng = np.random.default_rng(seed)
+    nk = 15
+    n_shells, beta = _draw_shells(rng, nk)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) % (1 << 63))
+    sig = default_sigma(H, W)
+    params = RING_PARAMS if ring else ("m", "s", "h")
+    ranges = dict(RING_GENE_RANGES, **GENE_RANGES)
+    P = torch.empty((len(params), nk, H, W), dtype=torch.float32, device=device)
+    for pi, p in enumerate(params):
+        lo, hi = ranges[p]
+        for k in range(nk):
+            P[pi, k] = _device_smooth_field(g, H, W, lo, hi, sig, device)
+    A = torch.zeros((3, H, W), dtype=torch.float32, device=device)
+    corners = torch.stack([torch.randint(0, H, (n_blobs,), generator=g, device=device),
+                           torch.randint(0, W, (n_blobs,), generator=g, device=device)], 1).cpu()
+    vals = torch.rand((n_blobs, 3, BLOB, BLOB), generator=g, device=device)
+    ar = torch.arange(BLOB, device=device)
+    for b in range(n_blobs):
+        y0, x0 = int(corners[b, 0]), int(corners[b, 1])
+        ys, xs = (y0 + ar) % H, (x0 + ar) % W
+        A[:, ys[:, None], xs[None, :]] = vals[b]
+    if per_blob_genes:
+        side = 2 * BLOB
+        sr = torch.arange(side, device=device)
+        lo = torch.tensor([ranges[p][0] for p in params], dtype=torch.float32, device=device)
+        hi = torch.tensor([ranges[p][1] for p in params], dtype=torch.float32, device=device)
+        genes = lo[None, :, None] + (hi - lo)[None, :, None] * torch.rand(
+            (n_blobs, len(params), nk), generator=g, device=device)
+        for b in range(n_blobs):
+            y0 = int(corners[b, 0]) + BLOB // 2 - side // 2
+            x0 = int(corners[b, 1]) + BLOB // 2 - side // 2
+            ys, xs = (y0 + sr) % H, (x0 + sr) % W
+            P[:, :, ys[:, None], xs[None, :]] = genes[b][:, :, None, None]
+    w = World(H=H, W=W, n_channels=3, n_kernels=nk, src=KERNEL_SRC_3CH, dst=KERNEL_DST_3CH,
+              R=R, n_shells=n_shells, beta=beta, dt=dt, localized=1, genotype_update=1,
+              m=None, s=None, h=None, eps=0.01, r_diff=1, A=None, P=None, name=name,
+              n_ring=n_ring if ring else 0)
+    return w, A, P
+
+
+def device_config4(n_worlds: int = 256, device: str = "cuda"):
+    """The batched workload drawn on the device: sides as in config4 (the same
+    per-world numpy streams decide them), each world from device_world seeded
+    by its stream's first 63-bit draw.  Returns a list of (World, A, P)."""
+    seqs = np.random.SeedSequence(SEED_BASE + 4).spawn(n_worlds)
+    out = []
+    for i, sq in enumerate(seqs):
+        rng = np.random.default_rng(sq)
+        side = C4_SIDES[int(rng.integers(len(C4_SIDES)))]
+        seed = int(rng.integers(1 << 62))
+        out.append(device_world(side, side, blobs_for_side(side), seed, name=f"batch{i}-{side}",
+                                device=device))
+    return out
+
+
+def device_config_ring(H: int = 4096, W: int = 4096, n_blobs: int = 2000, device: str = "cuda"):
+    """The 4096^2 ring-form workload (2000 blobs with their own 9 x 15 genes)
+    drawn on the device."""
+    return device_world(H, W, n_blobs, SEED_BASE + 6, per_blob_genes=True, ring=True,
+                        name=f"lenia-ring-3ch15k-{H}", device=device)

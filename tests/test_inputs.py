@@ -50,3 +50,33 @@ def test_device_state_layout():
     w1 = inputs.large_world(32, 32, seed=9, n_channels=1)
     A1, P1 = inputs.device_state(w1, seed=3, block=8, device="cpu")
     assert A1.shape == (1, 32, 32) and P1 is None
+
+
+def test_device_world_recipe_on_the_cpu():
+    """The device-drawn worlds (benchmark only) follow the numpy recipe: gene
+    planes uniform in their ranges with a correlation length of about 16
+    cells, 24 x 24 blobs of U[0, 1) values in all channels on an empty
+    state, per-blob genes constant on 48 x 48 squares; the ring form draws
+    its 9 gene types in the paper's order.  Run with torch on the CPU."""
+    import torch
+    w, A, P = inputs.device_world(128, 160, 6, seed=7, per_blob_genes=True, device="cpu")
+    assert A.dtype == torch.float32 and A.shape == (3, 128, 160) and P.shape == (3, 15, 128, 160)
+    assert w.A is None and w.P is None and w.n_ring == 0 and w.genotype_update == 1
+    for pi, p in enumerate(("m", "s", "h")):
+        lo, hi = inputs.GENE_RANGES[p]
+        assert float(P[pi].min()) >= lo and float(P[pi].max()) <= hi
+    # smooth fields: neighbouring cells nearly equal, cells 64 apart not
+    f = P[0, 3]
+    f = (f - f.mean()) / f.std()
+    c1 = float((f * torch.roll(f, 1, 1)).mean())
+    c64 = float((f * torch.roll(f, 64, 1)).mean())
+    assert c1 > 0.95 and abs(c64) < 0.5
+    occ = (A > 0).any(0)
+    assert 6 * 24 * 24 * 0.5 <= int(occ.sum()) <= 6 * 24 * 24
+    assert float(A.max()) < 1.0 and float(A.min()) == 0.0
+    wr, Ar, Pr = inputs.device_world(64, 64, 2, seed=8, ring=True, device="cpu")
+    assert wr.n_ring == 24 and Pr.shape == (9, 15, 64, 64)
+    ranges = dict(inputs.RING_GENE_RANGES, **inputs.GENE_RANGES)
+    for pi, p in enumerate(inputs.RING_PARAMS):
+        lo, hi = ranges[p]
+        assert float(Pr[pi].min()) >= lo and float(Pr[pi].max()) <= hi
