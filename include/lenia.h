@@ -219,6 +219,28 @@ LENIA_API lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const fl
                             float* gA_t, float* gP_t, float* gbeta, void* stream);
 
 /*
+ * lenia_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and arguments, with their workspaces (the potential and
+ * diffusion cotangents and the per-tile shell-height partials, about
+ * 240 B per cell with 15 kernels) in one static device array of
+ * LENIA_NOALLOC_WORKSPACE_BYTES per GPU instead of plan-owned memory.  The
+ * array is created with the library's code object on each GPU it runs on and
+ * lives until the process ends; its address is looked up on the first call
+ * on a device.  Worlds that need more than the array holds (above about
+ * 2.7e5 cells with 15 kernels) get LENIA_ERR_UNSUPPORTED, and a plan whose
+ * device is not current gets LENIA_ERR_STATE.  Results are bitwise those of
+ * lenia_backward.  All calls on one GPU share the array: calls that overlap
+ * in time on one GPU (two streams, two threads) race and must be serialized
+ * by the caller.  The call itself allocates nothing.
+ */
+#define LENIA_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+LENIA_API lenia_status lenia_backward_noalloc(lenia_plan_t p, const float* A_t, const float* P_t,
+                                              const void* saved, const float* gA_next,
+                                              const float* gP_next, float* gA_t, float* gP_t,
+                                              float* gbeta, void* stream);
+
+/*
  * The environmental and random operators of Algorithm 2 around each step of
  * a single-world plan with localized, updated genes (shell form):
  *   1. walls (Section 2.7): A and P are set to 0 on the wall cells of the

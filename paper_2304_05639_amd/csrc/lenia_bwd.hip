@@ -17,7 +17,10 @@
 // Three kernels: a per-cell pass, a tiled gather pass (convolution transpose,
 // diffusion transpose, shell-height partials per tile), and a fixed-order
 // reduction of the partials.  No float atomics: results are deterministic.
+#include <mutex>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "lenia.h"
 #include "lenia_device.h"
@@ -629,6 +632,37 @@ static bwd_launch_fn find_bwd(int table, int R, bool small)
     return nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace of lenia_backward_noalloc: a static device array, one copy per
+// GPU, held until the process ends.  Its address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and passed to the kernels
+// like the plan-owned workspaces of lenia_backward.  No element of it is read
+// before the call that reads it has written it (the gather and diffusion
+// transposes drop the values of cells without alpha through selects), so
+// nothing is cleared between calls.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;        // by device ordinal
+
+static lenia_status scratch_address(int dev, void** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e, "looking up the static adjoint workspace");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LENIA_OK;
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 // Adjoint workspace sizes of a world: ubar [NK][H][W], numbar [3NK][H][W]
 // (gene update only) and the per-tile shell-height partials, sized for the
 // larger tile count of the two gather tiles.
@@ -774,5 +808,44 @@ extern "C" lenia_status lenia_backward(lenia_plan_t p, const float* A_t, const f
                            p->bw.numbar, p->bw.part, (hipStream_t)stream);
     } catch (...) {
         return set_error(LENIA_ERR_STATE, "exception in lenia_backward");
+    }
+}
+
+extern "C" lenia_status lenia_backward_noalloc(lenia_plan_t p, const float* A_t, const float* P_t,
+                                               const void* saved, const float* gA_next,
+                                               const float* gP_next, float* gA_t, float* gP_t,
+                                               float* gbeta, void* stream)
+{
+    try {
+        lenia_status st = bwd_validate(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta);
+        if (st != LENIA_OK) return st;
+        const WorldPlan& w = p->worlds[0];
+        size_t sizes[3];
+        bwd_ws_sizes(w, sizes);
+        const size_t need = align256(sizes[0]) + align256(sizes[1]) + sizes[2];
+        if (need > kScratchBytes)
+            return set_error(LENIA_ERR_UNSUPPORTED,
+                             "lenia_backward_noalloc: this world needs " + std::to_string(need) +
+                                 " workspace bytes, the static workspace holds " +
+                                 std::to_string(kScratchBytes) +
+                                 " (about 2.7e5 cells with 15 kernels); use lenia_backward");
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (dev != p->device)
+            return set_error(LENIA_ERR_STATE, "the plan's device is not the current device");
+        if ((st = bwd_debug_checks(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta,
+                                   (hipStream_t)stream)) != LENIA_OK)
+            return st;
+        void* base = nullptr;
+        if ((st = scratch_address(dev, &base)) != LENIA_OK) return st;
+        char* b = (char*)base;
+        float* ubar = (float*)b;
+        float* numbar = sizes[1] ? (float*)(b + align256(sizes[0])) : nullptr;
+        float* part = (float*)(b + align256(sizes[0]) + align256(sizes[1]));
+        return bwd_enqueue(p, A_t, P_t, saved, gA_next, gP_next, gA_t, gP_t, gbeta, ubar, numbar,
+                           part, (hipStream_t)stream);
+    } catch (...) {
+        return set_error(LENIA_ERR_STATE, "exception in lenia_backward_noalloc");
     }
 }

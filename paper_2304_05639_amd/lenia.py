@@ -24,7 +24,7 @@ FLAG_CHECK_FINITE = 2
 API = ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan", "lenia_plan_batched",
        "lenia_step", "lenia_step_batched", "lenia_potentials", "lenia_saved_bytes", "lenia_backward",
        "lenia_step_evolve", "lenia_plan_get_info", "lenia_plan_destroy", "lenia_status_str",
-       "lenia_last_error", "lenia_debug_fail_alloc")
+       "lenia_last_error", "lenia_debug_fail_alloc", "lenia_backward_noalloc")
 
 
 class LeniaError(RuntimeError):
@@ -88,6 +88,7 @@ def lib():
         L.lenia_saved_bytes.argtypes = [vp]
         L.lenia_saved_bytes.restype = C.c_size_t
         L.lenia_backward.argtypes = [vp] + [vp] * 8 + [vp]
+        L.lenia_backward_noalloc.argtypes = [vp] + [vp] * 8 + [vp]
         L.lenia_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
         L.lenia_step_evolve.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.POINTER(Evolution),
                                         C.POINTER(Event), vp]
@@ -99,7 +100,8 @@ def lib():
         L.lenia_debug_fail_alloc.restype = None
         for name in ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan",
                      "lenia_plan_batched", "lenia_step", "lenia_step_batched",
-                     "lenia_potentials", "lenia_backward", "lenia_plan_get_info",
+                     "lenia_potentials", "lenia_backward", "lenia_backward_noalloc",
+                     "lenia_plan_get_info",
                      "lenia_plan_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -297,8 +299,9 @@ class Plan:
         return U
 
     def backward(self, A_t, P_t, saved, gA_next, gP_next, gA_t=None, gP_t=None, gbeta=None,
-                 stream=None):
-        """VJP of one step; returns (gA_t, gP_t, gbeta) (gbeta accumulated)."""
+                 stream=None, noalloc=False):
+        """VJP of one step; returns (gA_t, gP_t, gbeta) (gbeta accumulated).
+        noalloc: lenia_backward_noalloc (static workspace, no allocation)."""
         import torch
         _check_tensor(A_t, (self.C, self.H, self.W), "A_t")
         _check_tensor(P_t, (3, self.NK, self.H, self.W), "P_t")
@@ -312,9 +315,10 @@ class Plan:
         if gbeta is None:
             gbeta = torch.zeros(self.NK, 3, dtype=torch.float32, device=A_t.device)
         _check_tensor(gbeta, (self.NK, 3), "gbeta")
-        _check(lib().lenia_backward(self._h, _ptr(A_t), _ptr(P_t), _ptr(saved), _ptr(gA_next),
-                                    _ptr(gP_next), _ptr(gA_t), _ptr(gP_t), _ptr(gbeta),
-                                    C.c_void_p(_stream(stream))), "lenia_backward")
+        fn = lib().lenia_backward_noalloc if noalloc else lib().lenia_backward
+        _check(fn(self._h, _ptr(A_t), _ptr(P_t), _ptr(saved), _ptr(gA_next), _ptr(gP_next),
+                  _ptr(gA_t), _ptr(gP_t), _ptr(gbeta), C.c_void_p(_stream(stream))),
+               "lenia_backward_noalloc" if noalloc else "lenia_backward")
         return gA_t, gP_t, gbeta
 
     def close(self):
