@@ -491,6 +491,28 @@ def summarize(leg: str, fetch_glob: str, write_glob: str, window: dict, first: i
     print(json.dumps(out))
 
 
+def trace_summary(trace_glob: str, out_md: str, command: str):
+    """A markdown summary of a rocprofv3 --kernel-trace run of the benchmark:
+    per (kernel, grid) calls and durations, and the headline window (the
+    4096^2 step kernel's dispatches ADVANCE + W .. ADVANCE + W + K - 1 of the
+    default run, the headline leg being the first to launch it)."""
+    rows = _counter_rows(trace_glob)
+    by = {}
+    for r in rows:
+        key = (r["Kernel_Name"], int(r.get("Grid_Size", r.get("Grid_Size_X", 0)) or 0))
+        d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        by.setdefault(key, []).append((int(r["Dispatch_Id"]), d))
+    lines = [f"Kernel trace of `{command}`", "",
+             "| kernel | grid (threads) | calls | average ns | min ns | max ns |", "|---|---|---|---|---|---|"]
+    for (name, grid), v in sorted(by.items(), key=lambda kv: -sum(d for _, d in kv[1]))[:25]:
+        ds = [d for _, d in v]
+        lines.append(f"| `{name[:110]}` | {grid} | {len(ds)} | {sum(ds) / len(ds):.0f} | {min(ds)} | {max(ds)} |")
+    head = [(i, d) for (name, grid), v in by.items() if LEG_KERNEL["headline"] in name and grid == 4096 * 4096
+            for (i, d) in v]
+    head.sort()
+    return lines, head
+
+
 # ---- main ------------------------------------------------------------------------------
 
 def main():
@@ -509,7 +531,43 @@ def main():
                     help="write profiles/traffic_LEG.json from two counter runs (no GPU)")
     ap.add_argument("--command", action="append", default=[],
                     help="with --summarize: the profiling commands, recorded in the file")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_GLOB", "OUT_MD"),
+                    help="markdown summary of a rocprofv3 kernel trace of the default run (no GPU)")
+    ap.add_argument("--counter-summary", nargs=3, metavar=("LEG", "CSV_GLOB", "OUT_JSON"),
+                    help="per-counter averages over the leg's timed window (no GPU)")
     args = ap.parse_args()
+    if args.trace_summary:
+        tg, out_md = args.trace_summary
+        lines, head = trace_summary(tg, out_md, " ".join(args.command) or "python3 bench.py")
+        K, W = args.steps, args.warmup
+        win = head[ADVANCE + W:ADVANCE + W + K]
+        if len(win) == K:
+            avg = sum(d for _, d in win) / K
+            lines += ["", f"Headline window: the 4096^2 step kernel's dispatches {ADVANCE + W} to "
+                          f"{ADVANCE + W + K - 1} (of {len(head)}): average {avg:.0f} ns."]
+        with open(out_md, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
+    if args.counter_summary:
+        leg, cg, out_json = args.counter_summary
+        K, W = args.steps, args.warmup
+        first, count = {"headline": (ADVANCE + W, K), "ring": (RING_ADVANCE + W, K),
+                        "dft_f16": (2, 20), "batched": (-500, 500)}[leg]
+        rows = _counter_rows(cg)
+        names = sorted({r["Counter_Name"] for r in rows})
+        res = {"leg": leg, "kernel": LEG_KERNEL[leg], "counters": {}}
+        for cn in names:
+            per = _per_dispatch(rows, cn)
+            vals = [v for k, (n, v) in sorted(per.items()) if LEG_KERNEL[leg] in n]
+            start = first if first >= 0 else len(vals) + first
+            sel = vals[start:start + count]
+            res["counters"][cn] = sum(sel) / max(len(sel), 1)
+            res["dispatches"] = [start, len(sel), len(vals)]
+        with open(out_json, "w") as fh:
+            json.dump(res, fh, indent=1)
+        print(json.dumps(res))
+        return
     if args.summarize:
         leg, fg, wg = args.summarize
         K, W = args.steps, args.warmup
