@@ -464,13 +464,13 @@ def summarize(leg: str, fetch_glob: str, write_glob: str, window: dict, first: i
     w = _per_dispatch(_counter_rows(write_glob), "WRITE_SIZE")
     gib_kib = 1024.0 * 1024.0
 
-    def first(d, pat):
+    def first_match(d, pat):
         for k in sorted(d):
             if pat in d[k][0]:
                 return d[k][1]
         raise SystemExit(f"no dispatch matching {pat!r}")
-    fetch_factor = gib_kib / first(f, "reduce_kernel")
-    write_factor = gib_kib / first(w, "FillFunctor")
+    fetch_factor = gib_kib / first_match(f, "reduce_kernel")
+    write_factor = gib_kib / first_match(w, "FillFunctor")
     all_f = [v for k, (n, v) in sorted(f.items()) if LEG_KERNEL[leg] in n]
     all_w = [v for k, (n, v) in sorted(w.items()) if LEG_KERNEL[leg] in n]
     start = first if first >= 0 else len(all_f) + first
