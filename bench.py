@@ -55,7 +55,7 @@ LEG_SRCS = {
 # the kernel each leg's roofline is about (a substring of its name in the trace)
 LEG_KERNEL = {"headline": "step_kernel<lenia::Table3x15, 12, 8, 32>",
               "ring": "ring_step_kernel", "batched": "step_batch_kernel",
-              "dft_f16": "dft_conv_kernel<lenia::Table3x15, 12, _Float16>"}
+              "dft_f16": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_E"}   # as the trace names it
 
 
 def sources_sha(names) -> str:
@@ -261,9 +261,11 @@ def evolve_form(world, A, P, steps: int = 20, warmup: int = 5, r_oxy: int = 6,
 
 
 # MFMA instructions (16x16x32, 16384 flops each) per 64 x 64 tile of the DFT
-# forms: forward transforms 3 channels x (192 + 384), inverse 15 kernels x
-# (240 + 108); every product is issued three times (hi*hi, hi*lo, lo*hi).
-DFT_MFMA_PER_TILE = 3 * (192 + 384) + 15 * (240 + 108)
+# forms, every product issued three times (hi*hi, hi*lo, lo*hi): forward
+# transforms 3 channels x (192 + 384); per channel two pairs of kernels
+# sharing a row inverse (240) with both parts of the column inverse (216), and
+# one single kernel (240 + 108).
+DFT_MFMA_PER_TILE = 3 * (192 + 384) + 3 * (2 * (240 + 216) + (240 + 108))
 MFMA_FLOPS = 16 * 16 * 32 * 2
 
 

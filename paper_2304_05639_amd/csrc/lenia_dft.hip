@@ -12,6 +12,12 @@
 //   GEMM3  [Z_re; Z_im]^T    (64 x 2V)  = [U_re; U_im]^T [[C_V, -S_V], [S_V, C_V]]^T
 //   GEMM4  u_k               (V x V)    = [Z_re | Z_im] [C'_V; -S'_V]
 // where C_V / S_V keep the V output rows (columns) of the inverse transform.
+// Two kernels k1, k2 reading the same channel share one inverse transform:
+// Xh * Khat_k1 and Xh * Khat_k2 are each the spectrum of a real image, so the
+// inverse transform of U = Xh * Khat_k1 + i Xh * Khat_k2 is u_k1 + i u_k2;
+// GEMM3 runs once for the pair and GEMM4 forms both parts, the imaginary one
+// with [S'_V; C'_V].  With five kernels per channel that is two pairs and one
+// single kernel per channel.
 // Every GEMM runs on v_mfma_f32_16x16x32_bf16 (or _f16) with FP32
 // accumulation; each operand x is split as hi = e(x), lo = e(x - hi) in the
 // operand type e and a product is hi*hi + hi*lo + lo*hi: about 16 significant
@@ -104,6 +110,7 @@ struct DftTables {
     const void* f2;       // [2][128][128] hi, lo of [[C, S], [-S, C]]
     const void* f3;       // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
     const void* f4t;      // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
+    const void* f4ti;     // [2][48][128]  hi, lo of [S'_V; C'_V]^T (imaginary part)
     const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2, times 2^kUExp
 };
 
@@ -177,6 +184,7 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     const E* f2m = (const E*)g.t.f2;
     const E* f3m = (const E*)g.t.f3;
     const E* f4t = (const E*)g.t.f4t;
+    const E* f4ti = (const E*)g.t.f4ti;
     constexpr int V = DT - 2 * R;
     // LDS: the transformed channel being processed (fp32) + a scratch region
     // shared by the forward stages (Xs, Yt) and the inverse stages (Zc, and the
@@ -225,13 +233,15 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
         }
     }
     // GEMM4: wave w < 3 handles output column block w; B fragments in registers
-    ev8 b4h[4], b4l[4];
+    ev8 b4h[4], b4l[4], b4ih[4], b4il[4];
     {
         const int row = 16 * (wave < 3 ? wave : 0) + lr;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             b4h[ks] = ld8(f4t + row * DT2 + 32 * ks + lk);
             b4l[ks] = ld8(f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
+            b4ih[ks] = ld8(f4ti + row * DT2 + 32 * ks + lk);
+            b4il[ks] = ld8(f4ti + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
         }
     }
 
@@ -334,27 +344,50 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
         }
         __syncthreads();
 #pragma unroll 1
-        for (int slot = 0; slot < T::KPS; ++slot) {
-            const int k = T::kidx[s][slot];
+        for (int it = 0; it < (T::KPS + 1) / 2; ++it) {
+            const int k = T::kidx[s][2 * it];
+            const bool pair = (2 * it + 1 < T::KPS);
+            const int k2 = pair ? T::kidx[s][2 * it + 1] : k;
             const float* kh = g.t.khat + (size_t)k * DT * DT;
-            // the spectral product U = Xh * Khat (real spectrum, both halves), split
-            // into LDS once for all waves
-            for (int i = threadIdx.x; i < DT * (DT2 / 8); i += 256) {
-                const int f2 = i / (DT2 / 8), c8 = (i % (DT2 / 8)) * 8;
-                const f32x4 x0v = *(const f32x4*)(xh + f2 * XH_P + c8);
-                const f32x4 x1v = *(const f32x4*)(xh + f2 * XH_P + c8 + 4);
-                const f32x4 k0v = *(const f32x4*)(kh + f2 * DT + (c8 % DT));
-                const f32x4 k1v = *(const f32x4*)(kh + f2 * DT + (c8 % DT) + 4);
-                float u8[8];
+            const float* kh2 = g.t.khat + (size_t)k2 * DT * DT;
+            // the spectral product U = Xh * Khat_k (+ i Xh * Khat_k2 for a pair,
+            // halved so that it keeps the bound of one product), split into LDS
+            // once for all waves: 8 frequencies per thread and item, real part at
+            // column c8, imaginary part at column 64 + c8
+            const float ph = pair ? 0.5f : 1.f;
+            for (int i = threadIdx.x; i < DT * (DT / 8); i += 256) {
+                const int f2 = i / (DT / 8), c8 = (i % (DT / 8)) * 8;
+                const float* xr = xh + f2 * XH_P + c8;
+                const f32x4 r0 = *(const f32x4*)xr, r1 = *(const f32x4*)(xr + 4);
+                const f32x4 i0 = *(const f32x4*)(xr + DT), i1 = *(const f32x4*)(xr + DT + 4);
+                const f32x4 a0 = *(const f32x4*)(kh + f2 * DT + c8), a1 = *(const f32x4*)(kh + f2 * DT + c8 + 4);
+                float ure[8], uim[8];
+                if (pair) {
+                    const f32x4 b0 = *(const f32x4*)(kh2 + f2 * DT + c8);
+                    const f32x4 b1 = *(const f32x4*)(kh2 + f2 * DT + c8 + 4);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    u8[q] = x0v[q] * k0v[q];
-                    u8[4 + q] = x1v[q] * k1v[q];
+                    for (int q = 0; q < 4; ++q) {
+                        ure[q] = (r0[q] * a0[q] - i0[q] * b0[q]) * ph;
+                        ure[4 + q] = (r1[q] * a1[q] - i1[q] * b1[q]) * ph;
+                        uim[q] = (i0[q] * a0[q] + r0[q] * b0[q]) * ph;
+                        uim[4 + q] = (i1[q] * a1[q] + r1[q] * b1[q]) * ph;
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ure[q] = r0[q] * a0[q];
+                        ure[4 + q] = r1[q] * a1[q];
+                        uim[q] = i0[q] * a0[q];
+                        uim[4 + q] = i1[q] * a1[q];
+                    }
                 }
                 ev8 uh, ul;
-                split8<E>(u8, uh, ul);
+                split8<E>(ure, uh, ul);
                 *(ev8*)(ust_hi + f2 * UST_P + c8) = uh;
                 *(ev8*)(ust_lo + f2 * UST_P + c8) = ul;
+                split8<E>(uim, uh, ul);
+                *(ev8*)(ust_hi + f2 * UST_P + DT + c8) = uh;
+                *(ev8*)(ust_lo + f2 * UST_P + DT + c8) = ul;
             }
             __syncthreads();
             // GEMM3: Z^T (64 x 80) = Ust^T (64 x 128) F3^T; wave handles all 4 row blocks
@@ -396,9 +429,9 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
             __syncthreads();
             // GEMM4: u (48 x 48) = Zc (48 x 128) F4; wave w < 3 computes column block w
             if (wave < 3) {
-                f32x4 o[3];
+                f32x4 o[3], o2[3];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int m = 0; m < 3; ++m) o[m] = o2[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
                     const int k0 = 32 * ks + lk;
@@ -408,19 +441,25 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                         const ev8 ah = ld8(zc_hi + row * ZC_P + k0);
                         const ev8 al = ld8(zc_lo + row * ZC_P + k0);
                         o[m] = mma3<E>(ah, al, b4h[ks], b4l[ks], o[m]);
+                        if (pair) o2[m] = mma3<E>(ah, al, b4ih[ks], b4il[ks], o2[m]);
                     }
                 }
                 // u row p = 16m + ld + j, column q = 16w + lr
                 const int qx = 16 * wave + lr;
                 const int gx = x0 + qx;
                 if (qx < V && gx < W) {
+                    const float so = pair ? 2.f * sout : sout;
                     float* uk = g.U + (size_t)k * HW;
+                    float* uk2 = g.U + (size_t)k2 * HW;
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const int p = 16 * m + ld + j, gy = y0 + p;
-                            if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][j] * sout;
+                            if (p < V && gy < H) {
+                                uk[(size_t)gy * W + gx] = o[m][j] * so;
+                                if (pair) uk2[(size_t)gy * W + gx] = o2[m][j] * so;
+                            }
                         }
                 }
             }
@@ -488,7 +527,8 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
     const double tw = 2.0 * M_PI / DT;
     auto C = [&](int f, int i) { return std::cos(tw * (double)((f * i) % DT)); };
     auto S = [&](int f, int i) { return std::sin(tw * (double)((f * i) % DT)); };
-    std::vector<double> f1t(DT2 * DT), f2(DT2 * DT2), f3(80 * DT2, 0.0), f4t(ZC_ROWS * DT2, 0.0);
+    std::vector<double> f1t(DT2 * DT), f2(DT2 * DT2), f3(80 * DT2, 0.0), f4t(ZC_ROWS * DT2, 0.0),
+        f4ti(ZC_ROWS * DT2, 0.0);
     for (int c = 0; c < DT2; ++c)          // [C | -S]^T : row c, column j
         for (int j = 0; j < DT; ++j) f1t[c * DT + j] = (c < DT) ? C(c, j) : -S(c - DT, j);
     for (int r = 0; r < DT2; ++r)
@@ -512,6 +552,7 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         for (int k = 0; k < DT2; ++k) {
             const int f2i = k % DT;
             f4t[q * DT2 + k] = (k < DT) ? C(f2i, R + q) : -S(f2i, R + q);
+            f4ti[q * DT2 + k] = (k < DT) ? S(f2i, R + q) : C(f2i, R + q);
         }
     // hi = round(x), lo = round(x - hi) in the operand type of the plan's form
     const bool f16 = (p->conv == LENIA_CONV_DFT_SPLIT_F16);
@@ -564,7 +605,8 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
     const struct {
         const std::vector<double>* m;
         void** dst;
-    } mats[4] = {{&f1t, &w.dft_f1t}, {&f2, &w.dft_f2}, {&f3, &w.dft_f3}, {&f4t, &w.dft_f4t}};
+    } mats[5] = {{&f1t, &w.dft_f1t}, {&f2, &w.dft_f2}, {&f3, &w.dft_f3}, {&f4t, &w.dft_f4t},
+                 {&f4ti, &w.dft_f4ti}};
     for (const auto& mm : mats) {
         uint16_t* host = split(*mm.m);
         const size_t bytes = 2 * mm.m->size() * sizeof(uint16_t);
@@ -603,6 +645,7 @@ hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const
     a.t.f2 = w.dft_f2;
     a.t.f3 = w.dft_f3;
     a.t.f4t = w.dft_f4t;
+    a.t.f4ti = w.dft_f4ti;
     a.t.khat = w.dft_khat;
     a.H = w.H;
     a.W = w.W;

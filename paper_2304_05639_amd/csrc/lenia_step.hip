@@ -233,7 +233,7 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
             for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
         }
 #pragma unroll
-        for (int q = 0; q < NP; ++q) pst(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
+        for (int q = 0; q < NP; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
         if (wd.alpha_save) wd.alpha_save[ob >> 2] = alpha ? 1 : 0;
         if (wd.flags_out) {
             float su = 0.f;
@@ -296,7 +296,7 @@ __device__ __forceinline__ void write_dead_cells(const WorldArgs& wd, const floa
             const plane_t pl = plane(wd.P_out + (size_t)p * HW, pb);
 #pragma unroll
             for (int q = 0; q < Q; ++q)
-                if (in[q]) pst(pl, ob[q], 0.f);
+                if (in[q]) pst_stream(pl, ob[q], 0.f);
         }
     }
     if (wd.alpha_save) {
@@ -460,7 +460,7 @@ __device__ __forceinline__ void ring_epilogue_cell(const WorldArgs& wd, const fl
                     const int q = grp * 3 + i;
                     g[q] = diffuse_disk(v[grp & 1][i], cs, ncs);
                     alpha = alpha && (g[q] > eps);
-                    pst(plane(wd.P_out + (size_t)(q * NK + k) * HW, pb), ob, g[q]);
+                    pst_stream(plane(wd.P_out + (size_t)(q * NK + k) * HW, pb), ob, g[q]);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -492,7 +492,7 @@ __device__ __forceinline__ void ring_epilogue_cell(const WorldArgs& wd, const fl
         pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(alpha ? a[ch] + wd.dt * sum[ch] : a[ch]));
     if (!alpha) {
 #pragma unroll
-        for (int q = 0; q < NPG; ++q) pst(plane(wd.P_out + (size_t)q * HW, pb), ob, 0.f);
+        for (int q = 0; q < NPG; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, 0.f);
     }
 }
 
