@@ -51,11 +51,13 @@ LEG_SRCS = {
     "ring": ("lenia_step.hip", "lenia_device.h", "lenia_internal.h", "lenia_plan.cpp"),
     "batched": ("lenia_step.hip", "lenia_device.h", "lenia_internal.h", "lenia_plan.cpp"),
     "dft_f16": ("lenia_dft.hip", "lenia_device.h", "lenia_internal.h"),
+    "dft_epilogue": ("lenia_step.hip", "lenia_device.h", "lenia_internal.h"),
 }
 # the kernel each leg's roofline is about (a substring of its name in the trace)
 LEG_KERNEL = {"headline": "step_kernel<lenia::Table3x15, 12, 8, 32>",
               "ring": "ring_step_kernel", "batched": "step_batch_kernel",
-              "dft_f16": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_E"}   # as the trace names it
+              "dft_f16": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_E",   # as the trace names it
+              "dft_epilogue": "epilogue_kernel<lenia::Table3x15>"}
 
 
 def sources_sha(names) -> str:
@@ -261,11 +263,11 @@ def evolve_form(world, A, P, steps: int = 20, warmup: int = 5, r_oxy: int = 6,
 
 
 # MFMA instructions (16x16x32, 16384 flops each) per 64 x 64 tile of the DFT
-# forms, every product issued three times (hi*hi, hi*lo, lo*hi): forward
-# transforms 3 channels x (192 + 384); per channel two pairs of kernels
-# sharing a row inverse (240) with both parts of the column inverse (216), and
-# one single kernel (240 + 108).
-DFT_MFMA_PER_TILE = 3 * (192 + 384) + 3 * (2 * (240 + 216) + (240 + 108))
+# forms, every product issued three times (hi*hi, hi*lo, lo*hi): per channel
+# the half-spectrum forward transform, 16 output tiles x 2 k-steps (row DFT)
+# and 16 x 4 (column DFT); per kernel the inverse, 10 x 4 (columns) and 9 x 2
+# (rows, back to real values).
+DFT_MFMA_PER_TILE = 3 * 3 * (16 * 2 + 16 * 4) + 15 * 3 * (10 * 4 + 9 * 2)
 MFMA_FLOPS = 16 * 16 * 32 * 2
 
 
@@ -475,13 +477,19 @@ def summarize(leg: str, fetch_glob: str, write_glob: str, window: dict, first: i
     write_factor = gib_kib / first_match(w, "FillFunctor")
     all_f = [v for k, (n, v) in sorted(f.items()) if LEG_KERNEL[leg] in n]
     all_w = [v for k, (n, v) in sorted(w.items()) if LEG_KERNEL[leg] in n]
-    start = first if first >= 0 else len(all_f) + first
-    sel_f, sel_w = all_f[start:start + count], all_w[start:start + count]
-    if len(sel_f) != count or len(sel_w) != count:
+    # a counter run can miss a few records of graph-launched kernels; the
+    # window is then whatever that run holds of it (at least half), counted
+    # from the same end, and the dispatch counts of both runs are kept
+    def window_of(v):
+        start = first if first >= 0 else max(len(v) + first, 0)
+        return start, v[start:start + count]
+    (start, sel_f), (_, sel_w) = window_of(all_f), window_of(all_w)
+    if 2 * min(len(sel_f), len(sel_w)) < count:
         raise SystemExit(f"found {len(sel_f)} / {len(sel_w)} dispatches of {LEG_KERNEL[leg]}")
-    fk, wk = sum(sel_f) / count, sum(sel_w) / count
+    fk, wk = sum(sel_f) / len(sel_f), sum(sel_w) / len(sel_w)
     out = {"leg": leg, "kernel": LEG_KERNEL[leg], "kernel_sha": sources_sha(LEG_SRCS[leg]),
            "window": window, "dispatches": [start, count, len(all_f)],
+           "dispatches_used": [len(sel_f), len(sel_w)], "dispatches_recorded": [len(all_f), len(all_w)],
            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
            "fetch_factor": fetch_factor, "write_factor": write_factor,
            "bytes_per_launch": 1024.0 * (fk * fetch_factor + wk * write_factor),
@@ -555,7 +563,7 @@ def main():
         leg, cg, out_json = args.counter_summary
         K, W = args.steps, args.warmup
         first, count = {"headline": (ADVANCE + W, K), "ring": (RING_ADVANCE + W, K),
-                        "dft_f16": (2, 20), "batched": (-500, 500)}[leg]
+                        "dft_f16": (2, 20), "dft_epilogue": (-20, 20), "batched": (-500, 500)}[leg]
         rows = _counter_rows(cg)
         names = sorted({r["Counter_Name"] for r in rows})
         res = {"leg": leg, "kernel": LEG_KERNEL[leg], "counters": {}}
@@ -577,7 +585,8 @@ def main():
         windows = {"headline": ({"advance": ADVANCE, "warmup": W, "steps": K}, ADVANCE + W, K),
                    "ring": ({"advance": RING_ADVANCE, "warmup": W, "steps": K}, RING_ADVANCE + W, K),
                    "batched": ({"steps": 500}, -500, 500),
-                   "dft_f16": ({"reps": 20}, 2, 20)}
+                   "dft_f16": ({"reps": 20}, 2, 20),
+                   "dft_epilogue": ({"warmup": 5, "steps": 20}, -20, 20)}
         window, first, count = windows[leg]
         summarize(leg, fg, wg, window, first, count, args.command)
         return

@@ -4,20 +4,28 @@
 // (the 40 x 40 output tile plus an R-cell halo, R = 12) it equals the inverse
 // DFT of DFT(window) times the kernel's DFT (Section 2.1 computes the
 // convolution through the convolution theorem).  The kernel is even, so its
-// DFT is real.  With C[f][i] = cos(2 pi f i / 64), S[f][i] = sin(2 pi f i / 64)
-// and real-embedded complex matrices, per tile:
-//   GEMM1  [Y_re | Y_im]     (64 x 128) = X (64 x 64) [C | -S]            per channel
-//   GEMM2  [Xh_re; Xh_im]    (128 x 64) = [[C, S], [-S, C]] [Y_re; Y_im]  per channel
-//          U = Xh * Khat_k (real, 1/64^2 folded in)                        per kernel
-//   GEMM3  [Z_re; Z_im]^T    (64 x 2V)  = [U_re; U_im]^T [[C_V, -S_V], [S_V, C_V]]^T
-//   GEMM4  u_k               (V x V)    = [Z_re | Z_im] [C'_V; -S'_V]
-// where C_V / S_V keep the V output rows (columns) of the inverse transform.
-// Two kernels k1, k2 reading the same channel share one inverse transform:
-// Xh * Khat_k1 and Xh * Khat_k2 are each the spectrum of a real image, so the
-// inverse transform of U = Xh * Khat_k1 + i Xh * Khat_k2 is u_k1 + i u_k2;
-// GEMM3 runs once for the pair and GEMM4 forms both parts, the imaginary one
-// with [S'_V; C'_V].  With five kernels per channel that is two pairs and one
-// single kernel per channel.
+// DFT is real, and the window is real, so its DFT is Hermitian: only the
+// column frequencies b = 0..32 are formed.  Columns 0 and 32 of the row
+// transform are real (sin(0) = sin(pi j) = 0); they share one complex column,
+// Y0 + i Y32, which keeps every half spectrum at exactly 32 columns.  With
+// C[f][i] = cos(2 pi f i / 64), S[f][i] = sin(2 pi f i / 64) and
+// real-embedded complex matrices, per tile:
+//   GEMM1  [Y_re | Y_im]     (64 x 64)  = X (64 x 64) F1                  per channel
+//          F1 = [C_0 .. C_31 | (-1)^j, -S_1 .. -S_31] (column b of each half)
+//   GEMM2  [T_re; T_im]      (128 x 32) = [[C, S], [-S, C]] [Y_re; Y_im]  per channel
+//          T[a][b] = Xh[a][b] for b >= 1, and T[a][0] = Xh[a][0] + i Xh[a][32]
+//   U[a][b] = Xh[a][b] Khat_k[a][b] for b >= 1; the packed column holds
+//   U[a][0] + i U[a][32] = T[a] (K0 + K32) / 2 + conj(T[-a]) (K0 - K32) / 2
+//   with K0 = Khat_k[a][0], K32 = Khat_k[a][32]                           per kernel
+//   GEMM3  [Z_re; Z_im]^T    (32 x 2V)  = [U_re; U_im]^T [[C_V, -S_V], [S_V, C_V]]^T
+//   GEMM4  u_k               (V x V)    = [Z_re | Z_im] F4
+//          F4 row b (real part) = 2 cos(2 pi b (q + R) / 64), row 0 = 1;
+//          row 32 + b (imaginary part) = -2 sin(...), row 32 = (-1)^(q + R)
+// where C_V / S_V keep the V output rows of the inverse transform.  GEMM3's
+// column 0 is the inverse of two Hermitian columns, so its real and imaginary
+// parts are the real inverses of columns 0 and 32, and GEMM4 is the
+// half-spectrum inverse along b (each column b = 1..31 stands for itself and
+// its conjugate 64 - b).
 // Every GEMM runs on v_mfma_f32_16x16x32_bf16 (or _f16) with FP32
 // accumulation; each operand x is split as hi = e(x), lo = e(x - hi) in the
 // operand type e and a product is hi*hi + hi*lo + lo*hi: about 16 significant
@@ -25,13 +33,13 @@
 // stays a normal number, |x| >= 2^-3, so every operand is scaled by a power
 // of two that puts its largest possible magnitude just below 2^14 (far from
 // fp16's largest value, 65504): the DFT matrices (|x| <= 1) by 2^14 on the
-// host, the window by 2^a from its largest magnitude, and each intermediate
-// by the bound its GEMM implies (a K-term sum of products below 2^28).  An
-// element then loses precision only below 2^-17 of that bound, where its
-// absolute error (half of fp16's subnormal step) is 2^-39 of it.  The scales
-// are exact, so they cancel in the result and leave the bf16 form's rounding
-// unchanged.  The DFT matrices are built in FP64 on the host and split there;
-// data operands are split here.
+// host (F4, |x| <= 2, by 2^13), the window by 2^a from its largest magnitude,
+// and each intermediate by the bound its GEMM implies (a K-term sum of
+// products below 2^28).  An element then loses precision only below 2^-17 of
+// that bound, where its absolute error (half of fp16's subnormal step) is
+// 2^-39 of it.  The scales are exact, so they cancel in the result and leave
+// the bf16 form's rounding unchanged.  The DFT matrices are built in FP64 on
+// the host and split there; data operands are split here.
 //
 // MFMA operand layouts (16x16x32): lane l holds A[l % 16][8 (l / 16) + j] and
 // B[8 (l / 16) + j][l % 16] for j < 8; the 16 x 16 FP32 result has
@@ -84,34 +92,36 @@ struct Op<_Float16> {
     }
 };
 
-// Power-of-two scales of the operands (see the header): the DFT matrices
-// carry 2^14; GEMM1's output (64 terms below 2^28) is split at 2^-20, the
+// Power-of-two scales of the operands (see the header): F1..F3 carry 2^14 and
+// F4 2^13; GEMM1's output (64 terms below 2^28) is split at 2^-20, the
 // spectral product (the transformed channel, 128 terms below 2^28, times a
 // spectrum of magnitude <= 2^-12) at 2^-9, folded into the spectra, and
 // GEMM3's output (128 terms) at 2^-21.  With the window scaled by 2^a the
-// potentials come out scaled by 2^(a + 6).
+// potentials come out scaled by 2^(a + 5).
 constexpr int kMatExp = 14;
+constexpr int kF4Exp = 13;
 constexpr int kYExp = -20;
 constexpr int kUExp = -9;
 constexpr int kZExp = -21;
-constexpr int kOutExp = 6;
+constexpr int kOutExp = 5;
 
 constexpr int DT = 64;                   // DFT tile
-constexpr int DT2 = 128;                 // real-embedded complex dimension
-constexpr int XS_P = DT + 8;             // LDS row pitches (bf16 / fp32 elements)
+constexpr int DT2 = 128;                 // real-embedded complex dimension of a full axis
+constexpr int NB = 32;                   // half-spectrum columns (0 and 32 packed in column 0)
+constexpr int XS_P = DT + 8;             // LDS row pitches (operand-type / fp32 elements)
 constexpr int YT_P = DT2 + 8;
-constexpr int XH_P = DT2 + 4;
-constexpr int ZC_P = DT2 + 8;
-constexpr int ZC_ROWS = 48;
+constexpr int TH_P = DT2 + 4;
 constexpr int UST_P = DT2 + 8;
+constexpr int ZC_P = DT + 8;
+constexpr int ZC_ROWS = 48;              // GEMM4 rows (V <= 48)
+constexpr int F3_ROWS = 80;              // GEMM3 columns (2V <= 80)
 
 struct DftTables {
-    const void* f1t;      // [2][128][64]  hi, lo of [C | -S]^T
-    const void* f2;       // [2][128][128] hi, lo of [[C, S], [-S, C]]
-    const void* f3;       // [2][80][128]  hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
-    const void* f4t;      // [2][48][128]  hi, lo of [C'_V; -S'_V]^T (rows >= V zero)
-    const void* f4ti;     // [2][48][128]  hi, lo of [S'_V; C'_V]^T (imaginary part)
-    const float* khat;    // [NK][64 f2][64 f1] real kernel spectra / 64^2, times 2^kUExp
+    const void* f1t;      // [2][64 c][64 j]  hi, lo of F1^T
+    const void* f2;       // [2][128][128]    hi, lo of [[C, S], [-S, C]]
+    const void* f3;       // [2][80][128]     hi, lo of [[C_V, -S_V], [S_V, C_V]] (rows >= 2V zero)
+    const void* f4t;      // [2][48 q][64 k]  hi, lo of F4^T (rows >= V zero)
+    const float* khat;    // [NK][33 b][64 a] real kernel spectra / 64^2, times 2^kUExp
 };
 
 struct DftArgs {
@@ -177,33 +187,33 @@ __device__ __forceinline__ void st4_split(E* hi, E* lo, const f32x4& v)
 }
 
 template <class T, int R, class E>
-__global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
+__global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 {
     typedef typename Op<E>::v8 ev8;
     const E* f1t = (const E*)g.t.f1t;
     const E* f2m = (const E*)g.t.f2;
     const E* f3m = (const E*)g.t.f3;
     const E* f4t = (const E*)g.t.f4t;
-    const E* f4ti = (const E*)g.t.f4ti;
     constexpr int V = DT - 2 * R;
-    // LDS: the transformed channel being processed (fp32) + a scratch region
-    // shared by the forward stages (Xs, Yt) and the inverse stages (Zc, and the
-    // spectral product Ust of the current kernel, split once per workgroup)
-    constexpr int XH_FLOATS = DT * XH_P;
-    constexpr int FWD_E = 2 * DT * XS_P + 2 * DT * YT_P;
-    constexpr int INV_E = 2 * ZC_ROWS * ZC_P + 2 * DT * UST_P;
+    static_assert(V <= ZC_ROWS && 2 * V <= F3_ROWS, "output tile exceeds the GEMM layout");
+    // LDS (53 KB, three workgroups per CU): the half spectrum T of the channel
+    // being processed (fp32), plus a scratch region shared by the forward
+    // stages (Xs, Yt) and the inverse stages (the split spectral product Ust
+    // and Zc, which do not overlap each other)
+    constexpr int FWD_E = 2 * DT * XS_P + 2 * NB * YT_P;
+    constexpr int INV_E = 2 * NB * UST_P + 2 * ZC_ROWS * ZC_P;
     constexpr int SCRATCH_E = (FWD_E > INV_E) ? FWD_E : INV_E;
-    __shared__ float xh[XH_FLOATS];
+    __shared__ __attribute__((aligned(16))) float th[NB * TH_P];
     __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
     __shared__ float wmax[4];
     E* xs_hi = scr;
     E* xs_lo = scr + DT * XS_P;
     E* yt_hi = scr + 2 * DT * XS_P;
-    E* yt_lo = yt_hi + DT * YT_P;
-    E* zc_hi = scr;
-    E* zc_lo = scr + ZC_ROWS * ZC_P;
-    E* ust_hi = scr + 2 * ZC_ROWS * ZC_P;
-    E* ust_lo = ust_hi + DT * UST_P;
+    E* yt_lo = yt_hi + NB * YT_P;
+    E* ust_hi = scr;
+    E* ust_lo = scr + NB * UST_P;
+    E* zc_hi = scr + 2 * NB * UST_P;
+    E* zc_lo = zc_hi + ZC_ROWS * ZC_P;
 
     const int H = g.H, W = g.W;
     const size_t HW = (size_t)H * W;
@@ -214,13 +224,10 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
     const int lr = lane & 15, lk = (lane >> 4) * 8, ld = (lane >> 4) * 4;
     const bool single_wrap = (H >= DT) && (W >= DT);
 
-    // ---- per kernel: spectral product and inverse transform -----------------
-    // GEMM3 has 4 row blocks x 5 column blocks (2V rows of Z, padded to 80):
-    // wave w computes column block w for every row block, and row block w of
-    // column block 4, five tiles each; the B fragments of its two column
-    // blocks stay in registers.
-    constexpr int NB3 = (2 * V + 15) / 16;
-    static_assert(NB3 == 5, "GEMM3 is laid out for 5 column blocks");
+    // GEMM3 (Z^T, 32 x 80) has 2 row blocks x 5 column blocks: wave w takes
+    // column block w of both row blocks, and waves 0 and 1 also row block w of
+    // column block 4; the B fragments of a wave's column blocks stay in
+    // registers.  GEMM4 (u, 48 x 48, K = 64): wave w < 3 takes column block w.
     ev8 b3h[2][4], b3l[2][4];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -229,23 +236,25 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
         for (int ks = 0; ks < 4; ++ks) {
             const int row = 16 * nt + lr, k0 = 32 * ks + lk;
             b3h[q][ks] = ld8(f3m + row * DT2 + k0);
-            b3l[q][ks] = ld8(f3m + 80 * DT2 + row * DT2 + k0);
+            b3l[q][ks] = ld8(f3m + F3_ROWS * DT2 + row * DT2 + k0);
         }
     }
-    // GEMM4: wave w < 3 handles output column block w; B fragments in registers
-    ev8 b4h[4], b4l[4], b4ih[4], b4il[4];
+    ev8 b4h[2], b4l[2];
     {
         const int row = 16 * (wave < 3 ? wave : 0) + lr;
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            b4h[ks] = ld8(f4t + row * DT2 + 32 * ks + lk);
-            b4l[ks] = ld8(f4t + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
-            b4ih[ks] = ld8(f4ti + row * DT2 + 32 * ks + lk);
-            b4il[ks] = ld8(f4ti + ZC_ROWS * DT2 + row * DT2 + 32 * ks + lk);
+        for (int ks = 0; ks < 2; ++ks) {
+            b4h[ks] = ld8(f4t + row * DT + 32 * ks + lk);
+            b4l[ks] = ld8(f4t + ZC_ROWS * DT + row * DT + 32 * ks + lk);
         }
     }
+    // spectral-product work of this thread: column b, frequencies a8 .. a8 + 7.
+    // Column 0 (the packed one, extra work) falls to wave 3, which has the
+    // fewest GEMM3 tiles and no GEMM4 tile.
+    const int sp_b = ((threadIdx.x >> 3) + 8) & (NB - 1), sp_a8 = (threadIdx.x & 7) * 8;
 
     // ---- per source channel: forward transform, then its kernels ------------
+#pragma unroll 1
     for (int s = 0; s < T::C; ++s) {
         __syncthreads();
         // load the 64 x 64 window (wrapped) and its largest magnitude, then
@@ -281,40 +290,40 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
             st4_split<E>(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, win[it] * sx);
         }
         __syncthreads();
-        // GEMM1: wave w computes rows 16w..16w+15 of Y, all 8 column blocks
+        // GEMM1: wave w computes rows 16w..16w+15 of Y, all 4 column blocks
         {
-            f32x4 acc[8];
+            f32x4 acc[4];
 #pragma unroll
-            for (int n = 0; n < 8; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int k0 = 32 * ks + lk;
                 const ev8 ah = ld8(xs_hi + (16 * wave + lr) * XS_P + k0);
                 const ev8 al = ld8(xs_lo + (16 * wave + lr) * XS_P + k0);
 #pragma unroll
-                for (int n = 0; n < 8; ++n) {
+                for (int n = 0; n < 4; ++n) {
                     const int row = 16 * n + lr;
                     const ev8 bh = ld8(f1t + row * DT + k0);
-                    const ev8 bl = ld8(f1t + DT2 * DT + row * DT + k0);
+                    const ev8 bl = ld8(f1t + DT * DT + row * DT + k0);
                     acc[n] = mma3<E>(ah, al, bh, bl, acc[n]);
                 }
             }
-            // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 64][64 (c / 64) + i]
+            // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 32][64 (c / 32) + i]
 #pragma unroll
-            for (int n = 0; n < 8; ++n) {
+            for (int n = 0; n < 4; ++n) {
                 const int c = 16 * n + lr;
-                const int off = (c % DT) * YT_P + DT * (c / DT) + 16 * wave + ld;
+                const int off = (c % NB) * YT_P + DT * (c / NB) + 16 * wave + ld;
                 st4_split<E>(yt_hi + off, yt_lo + off, acc[n] * ldexpf(1.f, kYExp));
             }
         }
         __syncthreads();
-        // GEMM2: wave w computes row blocks 2w, 2w+1 of Xh, all 4 column blocks
+        // GEMM2: wave w computes row blocks 2w, 2w+1 of T, both column blocks
         {
-            f32x4 acc[2][4];
+            f32x4 acc[2][2];
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
                 const int k0 = 32 * ks + lk;
@@ -326,114 +335,107 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                     al[m] = ld8(f2m + DT2 * DT2 + row * DT2 + k0);
                 }
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
+                for (int n = 0; n < 2; ++n) {
                     const ev8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
                     const ev8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
 #pragma unroll
                     for (int m = 0; m < 2; ++m) acc[m][n] = mma3<E>(ah[m], al[m], bh, bl, acc[m][n]);
                 }
             }
-            // Xh row r = 16 (2w + m) + ld + j, column f2 = 16n + lr  ->  xh[s][f2][r]
+            // T row r = 16 (2w + m) + ld + j (re: a, im: 64 + a), column b = 16n + lr  ->  th[b][r]
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    const int f2 = 16 * n + lr, r = 16 * (2 * wave + m) + ld;
-                    *(f32x4*)(xh + f2 * XH_P + r) = acc[m][n];
+                for (int n = 0; n < 2; ++n) {
+                    const int b = 16 * n + lr, r = 16 * (2 * wave + m) + ld;
+                    *(f32x4*)(th + b * TH_P + r) = acc[m][n];
                 }
         }
         __syncthreads();
 #pragma unroll 1
-        for (int it = 0; it < (T::KPS + 1) / 2; ++it) {
-            const int k = T::kidx[s][2 * it];
-            const bool pair = (2 * it + 1 < T::KPS);
-            const int k2 = pair ? T::kidx[s][2 * it + 1] : k;
-            const float* kh = g.t.khat + (size_t)k * DT * DT;
-            const float* kh2 = g.t.khat + (size_t)k2 * DT * DT;
-            // the spectral product U = Xh * Khat_k (+ i Xh * Khat_k2 for a pair,
-            // halved so that it keeps the bound of one product), split into LDS
-            // once for all waves: 8 frequencies per thread and item, real part at
-            // column c8, imaginary part at column 64 + c8
-            const float ph = pair ? 0.5f : 1.f;
-            for (int i = threadIdx.x; i < DT * (DT / 8); i += 256) {
-                const int f2 = i / (DT / 8), c8 = (i % (DT / 8)) * 8;
-                const float* xr = xh + f2 * XH_P + c8;
+        for (int j = 0; j < T::KPS; ++j) {
+            const int k = T::kidx[s][j];
+            const float* kh = g.t.khat + (size_t)k * (NB + 1) * DT;
+            // the spectral product U = Xh * Khat_k, split into LDS once for
+            // all waves: real part at column a, imaginary part at 64 + a
+            {
+                const float* xr = th + sp_b * TH_P + sp_a8;
+                const float* kr = kh + sp_b * DT + sp_a8;
                 const f32x4 r0 = *(const f32x4*)xr, r1 = *(const f32x4*)(xr + 4);
                 const f32x4 i0 = *(const f32x4*)(xr + DT), i1 = *(const f32x4*)(xr + DT + 4);
-                const f32x4 a0 = *(const f32x4*)(kh + f2 * DT + c8), a1 = *(const f32x4*)(kh + f2 * DT + c8 + 4);
+                const f32x4 k0 = *(const f32x4*)kr, k1 = *(const f32x4*)(kr + 4);
                 float ure[8], uim[8];
-                if (pair) {
-                    const f32x4 b0 = *(const f32x4*)(kh2 + f2 * DT + c8);
-                    const f32x4 b1 = *(const f32x4*)(kh2 + f2 * DT + c8 + 4);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ure[q] = (r0[q] * a0[q] - i0[q] * b0[q]) * ph;
-                        ure[4 + q] = (r1[q] * a1[q] - i1[q] * b1[q]) * ph;
-                        uim[q] = (i0[q] * a0[q] + r0[q] * b0[q]) * ph;
-                        uim[4 + q] = (i1[q] * a1[q] + r1[q] * b1[q]) * ph;
-                    }
-                } else {
+                for (int q = 0; q < 4; ++q) {
+                    ure[q] = r0[q] * k0[q];
+                    ure[4 + q] = r1[q] * k1[q];
+                    uim[q] = i0[q] * k0[q];
+                    uim[4 + q] = i1[q] * k1[q];
+                }
+                if (sp_b == 0) {
+                    // packed column: T[a] (K0 + K32) / 2 + conj(T[-a]) (K0 - K32) / 2
+                    const float* k32 = kh + NB * DT + sp_a8;
+                    const f32x4 m0 = *(const f32x4*)k32, m1 = *(const f32x4*)(k32 + 4);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        ure[q] = r0[q] * a0[q];
-                        ure[4 + q] = r1[q] * a1[q];
-                        uim[q] = i0[q] * a0[q];
-                        uim[4 + q] = i1[q] * a1[q];
+                    for (int q = 0; q < 8; ++q) {
+                        const float K0 = (q < 4) ? k0[q] : k1[q - 4];
+                        const float K32 = (q < 4) ? m0[q] : m1[q - 4];
+                        const float tr = (q < 4) ? r0[q] : r1[q - 4];
+                        const float ti = (q < 4) ? i0[q] : i1[q - 4];
+                        const int am = (DT - (sp_a8 + q)) & (DT - 1);
+                        const float trm = th[am], tim = th[DT + am];
+                        const float P = 0.5f * (K0 + K32), Q = 0.5f * (K0 - K32);
+                        ure[q] = tr * P + trm * Q;
+                        uim[q] = ti * P - tim * Q;
                     }
                 }
                 ev8 uh, ul;
                 split8<E>(ure, uh, ul);
-                *(ev8*)(ust_hi + f2 * UST_P + c8) = uh;
-                *(ev8*)(ust_lo + f2 * UST_P + c8) = ul;
+                *(ev8*)(ust_hi + sp_b * UST_P + sp_a8) = uh;
+                *(ev8*)(ust_lo + sp_b * UST_P + sp_a8) = ul;
                 split8<E>(uim, uh, ul);
-                *(ev8*)(ust_hi + f2 * UST_P + DT + c8) = uh;
-                *(ev8*)(ust_lo + f2 * UST_P + DT + c8) = ul;
+                *(ev8*)(ust_hi + sp_b * UST_P + DT + sp_a8) = uh;
+                *(ev8*)(ust_lo + sp_b * UST_P + DT + sp_a8) = ul;
             }
-            __syncthreads();
-            // GEMM3: Z^T (64 x 80) = Ust^T (64 x 128) F3^T; wave handles all 4 row blocks
-            f32x4 acc[2][4];
+            __syncthreads();    // Ust is complete; the previous GEMM4 is done with Zc
+            // GEMM3: Z^T (32 x 80) = Ust^T (32 x 128) F3^T
+            {
+                f32x4 acc[2], acc4 = f32x4{0.f, 0.f, 0.f, 0.f};
+                acc[0] = acc[1] = acc4;
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int k0 = 32 * ks + lk;          // a, or 64 + a for the imaginary part
 #pragma unroll
-                for (int m = 0; m < 4; ++m) acc[q][m] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int k0 = 32 * ks + lk;          // f1 + 64 (im)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int f2 = 16 * m + lr;
-                    const ev8 ah = ld8(ust_hi + f2 * UST_P + k0);
-                    const ev8 al = ld8(ust_lo + f2 * UST_P + k0);
-                    acc[0][m] = mma3<E>(ah, al, b3h[0][ks], b3l[0][ks], acc[0][m]);
-                    if (m == wave) acc[1][0] = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc[1][0]);
+                    for (int m = 0; m < 2; ++m) {
+                        const int b = 16 * m + lr;
+                        const ev8 ah = ld8(ust_hi + b * UST_P + k0);
+                        const ev8 al = ld8(ust_lo + b * UST_P + k0);
+                        acc[m] = mma3<E>(ah, al, b3h[0][ks], b3l[0][ks], acc[m]);
+                        if (m == wave) acc4 = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc4);
+                    }
                 }
-            }
-            __syncthreads();    // every wave has read Ust; the previous GEMM4 is done with Zc
-            // Z^T row f2 = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][64 (p' >= V) + f2]
+                // Z^T row b = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][32 (p' >= V) + b]
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int nt = (q == 0) ? wave : 4;
-                const int pp = 16 * nt + lr;
-                if (pp < 2 * V) {
-                    const int p = (pp < V) ? pp : pp - V, col0 = (pp < V) ? 0 : DT;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        if (q == 1 && m != 0) break;
-                        // column block 4 holds row block `wave` only, in acc[1][0]
-                        const int mm = (q == 0) ? m : wave;
-                        const int off = p * ZC_P + col0 + 16 * mm + ld;
-                        st4_split<E>(zc_hi + off, zc_lo + off, acc[q][m] * ldexpf(1.f, kZExp));
+                for (int q = 0; q < 3; ++q) {
+                    if (q == 2 && wave >= 2) break;
+                    const int nt = (q < 2) ? wave : 4;
+                    const int m = (q < 2) ? q : wave;
+                    const int pp = 16 * nt + lr;
+                    if (pp < 2 * V) {
+                        const int p = (pp < V) ? pp : pp - V, col0 = (pp < V) ? 0 : NB;
+                        const int off = p * ZC_P + col0 + 16 * m + ld;
+                        st4_split<E>(zc_hi + off, zc_lo + off, ((q < 2) ? acc[q] : acc4) * ldexpf(1.f, kZExp));
                     }
                 }
             }
-            __syncthreads();
-            // GEMM4: u (48 x 48) = Zc (48 x 128) F4; wave w < 3 computes column block w
+            __syncthreads();    // Zc is complete; every wave has read Ust
+            // GEMM4: u (48 x 48) = Zc (48 x 64) F4; wave w < 3 computes column block w
             if (wave < 3) {
-                f32x4 o[3], o2[3];
+                f32x4 o[3];
 #pragma unroll
-                for (int m = 0; m < 3; ++m) o[m] = o2[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int m = 0; m < 3; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
+                for (int ks = 0; ks < 2; ++ks) {
                     const int k0 = 32 * ks + lk;
 #pragma unroll
                     for (int m = 0; m < 3; ++m) {
@@ -441,25 +443,19 @@ __global__ __launch_bounds__(256) void dft_conv_kernel(DftArgs g)
                         const ev8 ah = ld8(zc_hi + row * ZC_P + k0);
                         const ev8 al = ld8(zc_lo + row * ZC_P + k0);
                         o[m] = mma3<E>(ah, al, b4h[ks], b4l[ks], o[m]);
-                        if (pair) o2[m] = mma3<E>(ah, al, b4ih[ks], b4il[ks], o2[m]);
                     }
                 }
                 // u row p = 16m + ld + j, column q = 16w + lr
                 const int qx = 16 * wave + lr;
                 const int gx = x0 + qx;
                 if (qx < V && gx < W) {
-                    const float so = pair ? 2.f * sout : sout;
                     float* uk = g.U + (size_t)k * HW;
-                    float* uk2 = g.U + (size_t)k2 * HW;
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int p = 16 * m + ld + j, gy = y0 + p;
-                            if (p < V && gy < H) {
-                                uk[(size_t)gy * W + gx] = o[m][j] * so;
-                                if (pair) uk2[(size_t)gy * W + gx] = o2[m][j] * so;
-                            }
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const int p = 16 * m + ld + jj, gy = y0 + p;
+                            if (p < V && gy < H) uk[(size_t)gy * W + gx] = o[m][jj] * sout;
                         }
                 }
             }
@@ -519,7 +515,8 @@ static float bf16_value(uint16_t b)
 }
 
 // Host tables of the DFT form: the four transform matrices (FP64, split into
-// bf16 hi / lo) and the kernels' real spectra on the 64 x 64 torus.
+// hi / lo parts in the plan's operand type) and the kernels' real spectra on
+// the 64 x 64 torus, columns b = 0..32.
 lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
                               std::vector<void*>& keep)
 {
@@ -527,10 +524,15 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
     const double tw = 2.0 * M_PI / DT;
     auto C = [&](int f, int i) { return std::cos(tw * (double)((f * i) % DT)); };
     auto S = [&](int f, int i) { return std::sin(tw * (double)((f * i) % DT)); };
-    std::vector<double> f1t(DT2 * DT), f2(DT2 * DT2), f3(80 * DT2, 0.0), f4t(ZC_ROWS * DT2, 0.0),
-        f4ti(ZC_ROWS * DT2, 0.0);
-    for (int c = 0; c < DT2; ++c)          // [C | -S]^T : row c, column j
-        for (int j = 0; j < DT; ++j) f1t[c * DT + j] = (c < DT) ? C(c, j) : -S(c - DT, j);
+    std::vector<double> f1t(DT * DT), f2(DT2 * DT2), f3(F3_ROWS * DT2, 0.0), f4t(ZC_ROWS * DT, 0.0);
+    for (int c = 0; c < DT; ++c)           // F1^T : row c, column j
+        for (int j = 0; j < DT; ++j) {
+            const int b = c % NB;
+            double v;
+            if (c < NB) v = C(b, j);
+            else v = (b == 0) ? C(NB, j) : -S(b, j);
+            f1t[c * DT + j] = v;
+        }
     for (int r = 0; r < DT2; ++r)
         for (int k = 0; k < DT2; ++k) {
             const int rr = r % DT, kk = k % DT;
@@ -541,24 +543,26 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         }
     for (int pp = 0; pp < 2 * V; ++pp)     // rows of [Z_re; Z_im]
         for (int k = 0; k < DT2; ++k) {
-            const int p = pp % V, f1 = k % DT;
-            const double c = C(f1, R + p), sn = S(f1, R + p);
+            const int p = pp % V, a = k % DT;
+            const double c = C(a, R + p), sn = S(a, R + p);
             double v;
             if (pp < V) v = (k < DT) ? c : -sn;
             else v = (k < DT) ? sn : c;
             f3[pp * DT2 + k] = v;
         }
-    for (int q = 0; q < V; ++q)            // [C'_V; -S'_V]^T : row q, column k
-        for (int k = 0; k < DT2; ++k) {
-            const int f2i = k % DT;
-            f4t[q * DT2 + k] = (k < DT) ? C(f2i, R + q) : -S(f2i, R + q);
-            f4ti[q * DT2 + k] = (k < DT) ? S(f2i, R + q) : C(f2i, R + q);
+    for (int q = 0; q < V; ++q)            // F4^T : row q, column k (2 cos / -2 sin; 1 and (-1)^(q+R) at b = 0)
+        for (int k = 0; k < DT; ++k) {
+            const int b = k % NB;
+            double v;
+            if (k < NB) v = (b == 0) ? 1.0 : 2.0 * C(b, R + q);
+            else v = (b == 0) ? C(NB, R + q) : -2.0 * S(b, R + q);
+            f4t[q * DT + k] = v;
         }
     // hi = round(x), lo = round(x - hi) in the operand type of the plan's form
     const bool f16 = (p->conv == LENIA_CONV_DFT_SPLIT_F16);
-    auto split = [&](const std::vector<double>& mu) {
+    auto split = [&](const std::vector<double>& mu, int e) {
         std::vector<double> m(mu.size());
-        for (size_t i = 0; i < m.size(); ++i) m[i] = std::ldexp(mu[i], kMatExp);
+        for (size_t i = 0; i < m.size(); ++i) m[i] = std::ldexp(mu[i], e);
         uint16_t* out = new uint16_t[2 * m.size()];
         for (size_t i = 0; i < m.size(); ++i) {
             if (f16) {
@@ -575,9 +579,10 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         keep.push_back(out);
         return out;
     };
-    // kernel spectra: Khat[k][f2][f1] = sum_d K~(d) cos(2 pi (f1 dy + f2 dx)/64) / 64^2
+    // kernel spectra: Khat[k][b][a] = sum_d K~(d) cos(2 pi (a dy + b dx)/64) / 64^2, b <= 32
+    constexpr int NBK = NB + 1;
     std::vector<double> kt((size_t)DT * DT);
-    float* kh = new float[(size_t)w.NK * DT * DT];
+    float* kh = new float[(size_t)w.NK * NBK * DT];
     keep.push_back(kh);
     for (int k = 0; k < w.NK; ++k) {
         const int B = w.n_shells[k];
@@ -587,28 +592,29 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         for (int dy = -R; dy <= R; ++dy)
             for (int dx = -R; dx <= R; ++dx)
                 kt[((dy + DT) % DT) * DT + (dx + DT) % DT] += raw_kernel_tap(R, B, beta, dy, dx) / z;
-        // separable real DFT: first over dx (f2), then dy (f1); the kernel is even
-        std::vector<double> t1((size_t)DT * DT, 0.0);
+        // separable real DFT: first over dx (b), then dy (a); the kernel is even
+        std::vector<double> t1((size_t)DT * NBK, 0.0);
         for (int y = 0; y < DT; ++y)
-            for (int f = 0; f < DT; ++f) {
+            for (int b = 0; b < NBK; ++b) {
                 double acc = 0.0;
-                for (int x = 0; x < DT; ++x) acc += kt[y * DT + x] * C(f, x);
-                t1[y * DT + f] = acc;
+                for (int x = 0; x < DT; ++x) acc += kt[y * DT + x] * C(b, x);
+                t1[y * NBK + b] = acc;
             }
-        for (int f2i = 0; f2i < DT; ++f2i)
-            for (int f1 = 0; f1 < DT; ++f1) {
+        for (int b = 0; b < NBK; ++b)
+            for (int a = 0; a < DT; ++a) {
                 double acc = 0.0;
-                for (int y = 0; y < DT; ++y) acc += t1[y * DT + f2i] * C(f1, y);
-                kh[((size_t)k * DT + f2i) * DT + f1] = (float)std::ldexp(acc / (DT * DT), kUExp);
+                for (int y = 0; y < DT; ++y) acc += t1[y * NBK + b] * C(a, y);
+                kh[((size_t)k * NBK + b) * DT + a] = (float)std::ldexp(acc / (DT * DT), kUExp);
             }
     }
     const struct {
         const std::vector<double>* m;
+        int e;
         void** dst;
-    } mats[5] = {{&f1t, &w.dft_f1t}, {&f2, &w.dft_f2}, {&f3, &w.dft_f3}, {&f4t, &w.dft_f4t},
-                 {&f4ti, &w.dft_f4ti}};
+    } mats[4] = {{&f1t, kMatExp, &w.dft_f1t}, {&f2, kMatExp, &w.dft_f2}, {&f3, kMatExp, &w.dft_f3},
+                 {&f4t, kF4Exp, &w.dft_f4t}};
     for (const auto& mm : mats) {
-        uint16_t* host = split(*mm.m);
+        uint16_t* host = split(*mm.m, mm.e);
         const size_t bytes = 2 * mm.m->size() * sizeof(uint16_t);
         void* d = nullptr;
         if (device_alloc(&d, bytes) != hipSuccess)
@@ -619,7 +625,7 @@ lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s,
         hipError_t e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "uploading DFT tables");
     }
-    const size_t kbytes = (size_t)w.NK * DT * DT * sizeof(float);
+    const size_t kbytes = (size_t)w.NK * NBK * DT * sizeof(float);
     void* d = nullptr;
     if (device_alloc(&d, kbytes) != hipSuccess) return set_error(LENIA_ERR_OUT_OF_MEMORY, "spectra");
     p->allocations.push_back(d);
@@ -645,7 +651,6 @@ hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const
     a.t.f2 = w.dft_f2;
     a.t.f3 = w.dft_f3;
     a.t.f4t = w.dft_f4t;
-    a.t.f4ti = w.dft_f4ti;
     a.t.khat = w.dft_khat;
     a.H = w.H;
     a.W = w.W;

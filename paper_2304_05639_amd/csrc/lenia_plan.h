@@ -48,7 +48,6 @@ struct WorldPlan {
     void* dft_f2 = nullptr;        //   kernel spectra and the potentials workspace
     void* dft_f3 = nullptr;
     void* dft_f4t = nullptr;
-    void* dft_f4ti = nullptr;
     float* dft_khat = nullptr;
     float* dft_u = nullptr;        // [NK][H][W]
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
