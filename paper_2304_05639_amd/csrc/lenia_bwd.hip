@@ -141,11 +141,11 @@ __global__ __launch_bounds__(256) void bwd_cell_kernel(BwdArgs b)
             }
         }
     // forward growth and pre-clip update (same arithmetic and order as the step
-    // kernel: ascending kernel index within the channel)
+    // kernel: kdst lists the channel's kernels in its summation order)
     float sum = 0.f;
 #pragma unroll
-    for (int j = 0; j < KPD; ++j) sum += growth(u[j], pd[0][j], pd[1][j], pd[2][j]);
-    const float z = a + dt * sum;
+    for (int j = 0; j < KPD; ++j) sum = growth_acc(sum, u[j], pd[0][j], pd[1][j], pd[2][j]);
+    const float z = fmaf(dt, sum, a);   // as the forward step forms it
     const float zb = (z >= 0.f && z <= 1.f) ? g1 : 0.f;
     (b.gA + (size_t)c * HW)[idx] = zb;
     const float gb = dt * zb;

@@ -75,7 +75,17 @@ __device__ __forceinline__ float growth_bell(float d, float s)
 // G(u; m, s, h) = h (2 exp(-(u-m)^2 / (2 s^2)) - 1)
 __device__ __forceinline__ float growth(float u, float m, float s, float h)
 {
-    return h * (2.f * growth_bell(u - m, s) - 1.f);
+    return h * fmaf(2.f, growth_bell(u - m, s), -1.f);
+}
+
+// acc + G(u; m, s, h), the last multiply and the add fused.  Every kernel that
+// sums growth for the state update goes through this one expression, so the
+// forms that must agree bitwise (the per-cell epilogue, the fused DFT step, the
+// adjoint's recomputed update) round alike whatever the compiler's contraction
+// setting in their file.
+__device__ __forceinline__ float growth_acc(float acc, float u, float m, float s, float h)
+{
+    return fmaf(h, fmaf(2.f, growth_bell(u - m, s), -1.f), acc);
 }
 
 // LDS row pitch of a staged single-channel tile: tile width + halo, rounded up

@@ -126,9 +126,10 @@ struct DftTables {
 
 struct DftArgs {
     const float* A;       // [C][H][W]
-    float* U;             // [NK][H][W] potentials (output)
+    float* U;             // [NK][H][W] potentials (output of the potentials-only kernel)
     DftTables t;
     int H, W, tiles_x, n_tiles;
+    WorldArgs wd;         // the fused step: genes in, A' and P' out (MODE_LOCAL_UPDATE)
 };
 
 template <class E>
@@ -163,6 +164,19 @@ __device__ __forceinline__ void split8(const float (&x)[8], typename Op<E>::v8& 
 template <class E>
 __device__ __forceinline__ typename Op<E>::v8 ld8(const E* p) { return *(const typename Op<E>::v8*)p; }
 
+// A buffer descriptor over a table of `bytes` bytes.
+__device__ __forceinline__ plane_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// 8 operand-type elements (16 bytes) at byte offset off + soff of a table.
+template <class E>
+__device__ __forceinline__ typename Op<E>::v8 bld8(plane_t r, uint32_t off, int soff)
+{
+    return __builtin_bit_cast(typename Op<E>::v8, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, soff, 0));
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
 #pragma unroll
@@ -186,12 +200,52 @@ __device__ __forceinline__ void st4_split(E* hi, E* lo, const f32x4& v)
     *(typename Op<E>::v4*)lo = l;
 }
 
-template <class T, int R, class E>
+// A workgroup barrier for LDS traffic only: this wave's LDS accesses complete,
+// then s_barrier.  Vector-memory operations stay in flight (the gene planes'
+// DMA into LDS, global stores); the memory clobber keeps the compiler from
+// moving memory accesses across it.  Waves of a workgroup exchange data only
+// through LDS here.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// The same after this wave's vector-memory operations (its DMA into LDS) have
+// completed too.
+__device__ __forceinline__ void dma_barrier()
+{
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Gene diffusion of one cell from a staged plane (side hs, the cell at c):
+// the disk values in the epilogue's order up, left, centre, right, down.
+__device__ __forceinline__ float diffuse_staged(const float* g, int c, int hs, float cs, float ncs)
+{
+    const float v[5] = {g[c - hs], g[c - 1], g[c], g[c + 1], g[c + hs]};
+    return diffuse_disk(v, cs, ncs);
+}
+
+// Torus coordinate of any integer position.
+__device__ __forceinline__ int wrap_any(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// The fused step (FUSED = true) replaces the potentials' trip through HBM:
+// each u_k goes from GEMM4 to LDS, and every thread carries the growth sums
+// and the alpha test of its cells from one kernel to the next.  The three
+// gene planes a kernel's growth reads (m, s, h) are staged into LDS with the
+// tile's 1-cell ring by direct-to-LDS buffer loads issued when the kernel's
+// turn begins, so their latency runs under its transform.  The result is the
+// epilogue's, bitwise: the same diffusion, test and growth arithmetic, the
+// growth summed in the same kernel order.
+template <class T, int R, class E, bool FUSED>
 __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 {
     typedef typename Op<E>::v8 ev8;
-    const E* f1t = (const E*)g.t.f1t;
-    const E* f2m = (const E*)g.t.f2;
+    const plane_t f1r = make_rsrc(g.t.f1t, 2 * DT * DT * sizeof(E));
+    const plane_t f2r = make_rsrc(g.t.f2, 2 * DT2 * DT2 * sizeof(E));
     const E* f3m = (const E*)g.t.f3;
     const E* f4t = (const E*)g.t.f4t;
     constexpr int V = DT - 2 * R;
@@ -206,6 +260,16 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
     __shared__ __attribute__((aligned(16))) float th[NB * TH_P];
     __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
     __shared__ float wmax[4];
+    // fused step: the staged gene planes (side V + 2, whole DMA rounds of the
+    // four waves per plane) and u_k of the current kernel, which takes the
+    // place of Ust once GEMM3 has read it
+    constexpr int HS = V + 2;
+    constexpr int NGI = (HS * HS + 255) / 256;      // DMA instructions per wave and plane
+    constexpr int GSLOT = 256 * NGI;
+    constexpr int NCR = (V * V + 255) / 256;        // cells per thread
+    static_assert(V * V * 4 <= 2 * NB * UST_P * (int)sizeof(E), "u_k must fit in Ust");
+    __shared__ __attribute__((aligned(16))) float gst[FUSED ? 3 * GSLOT : 1];
+    float* ut = (float*)scr;
     E* xs_hi = scr;
     E* xs_lo = scr + DT * XS_P;
     E* yt_hi = scr + 2 * DT * XS_P;
@@ -252,31 +316,88 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
     // Column 0 (the packed one, extra work) falls to wave 3, which has the
     // fewest GEMM3 tiles and no GEMM4 tile.
     const int sp_b = ((threadIdx.x >> 3) + 8) & (NB - 1), sp_a8 = (threadIdx.x & 7) * 8;
+    // this thread's 16 window elements: rows r = threadIdx.x / 16 + 16 it,
+    // columns c4 .. c4 + 3 (the same for every it), wrapped on the torus; the
+    // byte offset in a plane is wrow[it] + wcol[j]
+    const uint32_t pb = 4u * (uint32_t)HW;
+    constexpr int NWIN = DT * DT / 4 / 256;
+    uint32_t wrow[NWIN], wcol[4];
+#pragma unroll
+    for (int it = 0; it < NWIN; ++it) {
+        const int r = (threadIdx.x + 256 * it) / (DT / 4);
+        int gy = y0 - R + r, gx = 0;
+        wrap2(gy, gx, H, W, single_wrap);
+        wrow[it] = 4u * (uint32_t)gy * (uint32_t)W;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int gy = 0, gx = x0 - R + (threadIdx.x % (DT / 4)) * 4 + j;
+        wrap2(gy, gx, H, W, single_wrap);
+        wcol[j] = 4u * (uint32_t)gx;
+    }
+
+    // fused step: the per-lane offsets of the staged gene window (DMA
+    // instruction i of wave w loads window elements 256 i + 64 w + lane, row
+    // by row from (y0 - 1, x0 - 1) on the torus), and the state of this
+    // thread's cells ci = threadIdx.x + 256 r of the V x V tile: growth sums
+    // per target channel and the position (in the kernel order the tile
+    // follows) where alpha failed, kAlive while it holds, -1 off the world
+    const WorldArgs& wd = g.wd;
+    constexpr int kAlive = T::NK;
+    uint32_t goff[FUSED ? NGI : 1];
+    float gsum[FUSED ? NCR : 1][T::C];
+    int dead_at[FUSED ? NCR : 1];
+    if constexpr (FUSED) {
+#pragma unroll
+        for (int i = 0; i < NGI; ++i) {
+            const int e = 256 * i + 64 * wave + lane;
+            uint32_t o = 0;
+            if (e < HS * HS) {
+                const int row = e / HS, col = e - row * HS;
+                const int gy = wrap_any(y0 - 1 + row, H), gx = wrap_any(x0 - 1 + col, W);
+                o = 4u * ((uint32_t)gy * (uint32_t)W + (uint32_t)gx);
+            }
+            goff[i] = o;
+        }
+#pragma unroll
+        for (int r = 0; r < NCR; ++r) {
+            const int ci = threadIdx.x + 256 * r;
+            const int p = ci / V, q = ci - (ci / V) * V;
+            dead_at[r] = (ci < V * V && y0 + p < H && x0 + q < W) ? kAlive : -1;
+#pragma unroll
+            for (int c = 0; c < T::C; ++c) gsum[r][c] = 0.f;
+        }
+    }
 
     // ---- per source channel: forward transform, then its kernels ------------
 #pragma unroll 1
     for (int s = 0; s < T::C; ++s) {
-        __syncthreads();
+        // the forward transforms' tables are read again for each channel:
+        // an opaque zero offset keeps the compiler from hoisting these
+        // loop-invariant loads out of the channel loop, where they would hold
+        // 128 registers for the whole tile
+        int zoff;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
+        lds_barrier();
         // load the 64 x 64 window (wrapped) and its largest magnitude, then
         // stage it scaled by 2^a (largest magnitude below 2^14) as hi / lo
-        constexpr int NWIN = DT * DT / 4 / 256;
         f32x4 win[NWIN];
         float vmax = 0.f;
+        const plane_t apl = plane(g.A + (size_t)s * HW, pb);
+        // (the row offsets pass through an empty asm statement, so that the
+        // 16 sums are formed here rather than kept live across the loop)
 #pragma unroll
-        for (int it = 0; it < NWIN; ++it) {
-            const int i = threadIdx.x + 256 * it;
-            const int r = i / (DT / 4), c4 = (i % (DT / 4)) * 4;
+        for (int it = 0; it < NWIN; ++it) asm volatile("" : "+v"(wrow[it]));
+#pragma unroll
+        for (int it = 0; it < NWIN; ++it)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                int gy = y0 - R + r, gx = x0 - R + c4 + j;
-                wrap2(gy, gx, H, W, single_wrap);
-                win[it][j] = g.A[(size_t)s * HW + (size_t)gy * W + gx];
+                win[it][j] = pld(apl, wrow[it] + wcol[j]);
                 vmax = fmaxf(vmax, fabsf(win[it][j]));
             }
-        }
         vmax = wave_max(vmax);
         if (lane == 0) wmax[wave] = vmax;
-        __syncthreads();
+        lds_barrier();
         vmax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
         int ea = 0;
         (void)frexpf(vmax, &ea);                        // vmax < 2^ea
@@ -289,8 +410,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
             const int r = i / (DT / 4), c4 = (i % (DT / 4)) * 4;
             st4_split<E>(xs_hi + r * XS_P + c4, xs_lo + r * XS_P + c4, win[it] * sx);
         }
-        __syncthreads();
-        // GEMM1: wave w computes rows 16w..16w+15 of Y, all 4 column blocks
+        lds_barrier();
+        // GEMM1: wave w computes rows 16w..16w+15 of Y, all 4 column blocks;
+        // each k-step's eight B fragments are loaded before its products
         {
             f32x4 acc[4];
 #pragma unroll
@@ -298,15 +420,17 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks) {
                 const int k0 = 32 * ks + lk;
+                ev8 bh[4], bl[4];
+#pragma unroll
+                for (int n = 0; n < 4; ++n) {
+                    const uint32_t o = 2u * (uint32_t)((16 * n + lr) * DT + k0);
+                    bh[n] = bld8<E>(f1r, o, zoff);
+                    bl[n] = bld8<E>(f1r, o + 2u * DT * DT, zoff);
+                }
                 const ev8 ah = ld8(xs_hi + (16 * wave + lr) * XS_P + k0);
                 const ev8 al = ld8(xs_lo + (16 * wave + lr) * XS_P + k0);
 #pragma unroll
-                for (int n = 0; n < 4; ++n) {
-                    const int row = 16 * n + lr;
-                    const ev8 bh = ld8(f1t + row * DT + k0);
-                    const ev8 bl = ld8(f1t + DT * DT + row * DT + k0);
-                    acc[n] = mma3<E>(ah, al, bh, bl, acc[n]);
-                }
+                for (int n = 0; n < 4; ++n) acc[n] = mma3<E>(ah, al, bh[n], bl[n], acc[n]);
             }
             // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 32][64 (c / 32) + i]
 #pragma unroll
@@ -316,8 +440,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 st4_split<E>(yt_hi + off, yt_lo + off, acc[n] * ldexpf(1.f, kYExp));
             }
         }
-        __syncthreads();
-        // GEMM2: wave w computes row blocks 2w, 2w+1 of T, both column blocks
+        lds_barrier();
+        // GEMM2: wave w computes row blocks 2w, 2w+1 of T, both column blocks;
+        // the A fragments of two k-steps are loaded at a time
         {
             f32x4 acc[2][2];
 #pragma unroll
@@ -325,21 +450,27 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                 for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int k0 = 32 * ks + lk;
-                ev8 ah[2], al[2];
+            for (int kh = 0; kh < 2; ++kh) {
+                ev8 ah[2][2], al[2][2];
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const int row = 16 * (2 * wave + m) + lr;
-                    ah[m] = ld8(f2m + row * DT2 + k0);
-                    al[m] = ld8(f2m + DT2 * DT2 + row * DT2 + k0);
-                }
+                for (int kq = 0; kq < 2; ++kq)
 #pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    const ev8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
-                    const ev8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
+                    for (int m = 0; m < 2; ++m) {
+                        const int row = 16 * (2 * wave + m) + lr;
+                        const uint32_t o = 2u * (uint32_t)(row * DT2 + 32 * (2 * kh + kq) + lk);
+                        ah[kq][m] = bld8<E>(f2r, o, zoff);
+                        al[kq][m] = bld8<E>(f2r, o + 2u * DT2 * DT2, zoff);
+                    }
 #pragma unroll
-                    for (int m = 0; m < 2; ++m) acc[m][n] = mma3<E>(ah[m], al[m], bh, bl, acc[m][n]);
+                for (int kq = 0; kq < 2; ++kq) {
+                    const int k0 = 32 * (2 * kh + kq) + lk;
+#pragma unroll
+                    for (int n = 0; n < 2; ++n) {
+                        const ev8 bh = ld8(yt_hi + (16 * n + lr) * YT_P + k0);
+                        const ev8 bl = ld8(yt_lo + (16 * n + lr) * YT_P + k0);
+#pragma unroll
+                        for (int m = 0; m < 2; ++m) acc[m][n] = mma3<E>(ah[kq][m], al[kq][m], bh, bl, acc[m][n]);
+                    }
                 }
             }
             // T row r = 16 (2w + m) + ld + j (re: a, im: 64 + a), column b = 16n + lr  ->  th[b][r]
@@ -351,11 +482,23 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                     *(f32x4*)(th + b * TH_P + r) = acc[m][n];
                 }
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll 1
         for (int j = 0; j < T::KPS; ++j) {
             const int k = T::kidx[s][j];
             const float* kh = g.t.khat + (size_t)k * (NB + 1) * DT;
+            if constexpr (FUSED) {
+                // stage gene planes k, NK + k, 2 NK + k (m, s, h of kernel k)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const plane_t pl = plane(wd.P + (size_t)(q * T::NK + k) * HW, pb);
+#pragma unroll
+                    for (int i = 0; i < NGI; ++i)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            pl, (__attribute__((address_space(3))) void*)(gst + q * GSLOT + 256 * i + 64 * wave),
+                            4, (int)goff[i], 0, 0, 0);
+                }
+            }
             // the spectral product U = Xh * Khat_k, split into LDS once for
             // all waves: real part at column a, imaginary part at 64 + a
             {
@@ -397,7 +540,7 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 *(ev8*)(ust_hi + sp_b * UST_P + DT + sp_a8) = uh;
                 *(ev8*)(ust_lo + sp_b * UST_P + DT + sp_a8) = ul;
             }
-            __syncthreads();    // Ust is complete; the previous GEMM4 is done with Zc
+            lds_barrier();    // Ust is complete; the previous GEMM4 is done with Zc
             // GEMM3: Z^T (32 x 80) = Ust^T (32 x 128) F3^T
             {
                 f32x4 acc[2], acc4 = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -428,7 +571,7 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                     }
                 }
             }
-            __syncthreads();    // Zc is complete; every wave has read Ust
+            lds_barrier();    // Zc is complete; every wave has read Ust
             // GEMM4: u (48 x 48) = Zc (48 x 64) F4; wave w < 3 computes column block w
             if (wave < 3) {
                 f32x4 o[3];
@@ -448,7 +591,17 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 // u row p = 16m + ld + j, column q = 16w + lr
                 const int qx = 16 * wave + lr;
                 const int gx = x0 + qx;
-                if (qx < V && gx < W) {
+                if constexpr (FUSED) {
+                    if (qx < V) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj) {
+                                const int p = 16 * m + ld + jj;
+                                if (p < V) ut[p * V + qx] = o[m][jj] * sout;
+                            }
+                    }
+                } else if (qx < V && gx < W) {
                     float* uk = g.U + (size_t)k * HW;
 #pragma unroll
                     for (int m = 0; m < 3; ++m)
@@ -459,33 +612,131 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                         }
                 }
             }
+            if constexpr (FUSED) {
+                // diffusion, alpha test and growth of kernel k at this
+                // thread's cells, from u_k and the staged genes; the new gene
+                // values go out now (0 where alpha has failed)
+                dma_barrier();
+                const int pos = s * T::KPS + j;
+                const int dk = T::dst[k];
+                const float eps = wd.eps, cs = wd.cnt_scale, ncs = wd.cnt_bias;
+                const plane_t o0 = plane(wd.P_out + (size_t)k * HW, pb);
+                const plane_t o1 = plane(wd.P_out + (size_t)(T::NK + k) * HW, pb);
+                const plane_t o2 = plane(wd.P_out + (size_t)(2 * T::NK + k) * HW, pb);
+                // cell coordinates are formed here from an opaque thread index
+                // (kept across the loop they would take registers the
+                // transforms need)
+                int tid = threadIdx.x;
+                asm volatile("" : "+v"(tid));
+#pragma unroll
+                for (int r = 0; r < NCR; ++r) {
+                    if (dead_at[r] < 0) continue;
+                    const int ci = tid + 256 * r;
+                    const int p = ci / V, q = ci - (ci / V) * V;
+                    float pd0 = 0.f, pd1 = 0.f, pd2 = 0.f;
+                    if (dead_at[r] == kAlive) {
+                        const float u = ut[ci];
+                        bool alive = u > eps;
+                        if (alive) {
+                            const int c = (p + 1) * HS + q + 1;
+                            pd0 = diffuse_staged(gst, c, HS, cs, ncs);
+                            pd1 = diffuse_staged(gst + GSLOT, c, HS, cs, ncs);
+                            pd2 = diffuse_staged(gst + 2 * GSLOT, c, HS, cs, ncs);
+                            alive = (pd0 > eps) && (pd1 > eps) && (pd2 > eps);
+                        }
+                        if (alive) {
+#pragma unroll
+                            for (int c = 0; c < T::C; ++c)
+                                if (c == dk) gsum[r][c] = growth_acc(gsum[r][c], u, pd0, pd1, pd2);
+                        } else {
+                            dead_at[r] = pos;
+                            pd0 = pd1 = pd2 = 0.f;
+                        }
+                    }
+                    const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
+                    pst_stream(o0, ob, pd0);
+                    pst_stream(o1, ob, pd1);
+                    pst_stream(o2, ob, pd2);
+                    // one cell at a time: hoisting every cell's 15 LDS reads
+                    // ahead would take more registers than the wave has
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                lds_barrier();    // u_k and the staged genes are free again
+            }
+        }
+    }
+    if constexpr (FUSED) {
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        // cells whose alpha failed after the first kernel: the gene planes of
+        // the kernels before that one hold diffused values, cleared here
+        int need = 0;
+#pragma unroll
+        for (int r = 0; r < NCR; ++r) need |= (dead_at[r] > 0 && dead_at[r] < kAlive) ? 1 : 0;
+        if (__any(need)) {
+#pragma unroll 1
+            for (int pos = 0; pos + 1 < T::NK; ++pos) {
+                const int kk = T::kidx[pos / T::KPS][pos % T::KPS];
+                const plane_t z0 = plane(wd.P_out + (size_t)kk * HW, pb);
+                const plane_t z1 = plane(wd.P_out + (size_t)(T::NK + kk) * HW, pb);
+                const plane_t z2 = plane(wd.P_out + (size_t)(2 * T::NK + kk) * HW, pb);
+#pragma unroll
+                for (int r = 0; r < NCR; ++r) {
+                    if (pos < dead_at[r] && dead_at[r] < kAlive) {
+                        const int ci = tid + 256 * r;
+                        const int p = ci / V, q = ci - (ci / V) * V;
+                        const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
+                        pst_stream(z0, ob, 0.f);
+                        pst_stream(z1, ob, 0.f);
+                        pst_stream(z2, ob, 0.f);
+                    }
+                }
+            }
+        }
+        // A' = clip01(A + dt * sum), the sum counting only where alpha holds
+        // (one fused multiply-add, as the per-cell epilogue forms it; this
+        // file compiles without contraction)
+#pragma unroll
+        for (int r = 0; r < NCR; ++r) {
+            if (dead_at[r] < 0) continue;
+            const int ci = tid + 256 * r;
+            const int p = ci / V, q = ci - (ci / V) * V;
+            const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
+            const bool alive = dead_at[r] == kAlive;
+#pragma unroll
+            for (int c = 0; c < T::C; ++c) {
+                const float a = pld(plane(wd.A + (size_t)c * HW, pb), ob);
+                pst(plane(wd.A_out + (size_t)c * HW, pb), ob, clip01(fmaf(wd.dt, alive ? gsum[r][c] : 0.f, a)));
+            }
         }
     }
 }
 
-template <class T, int R, class E>
+template <class T, int R, class E, bool FUSED>
 hipError_t launch_dft(const DftArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((dft_conv_kernel<T, R, E>), dim3(a.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((dft_conv_kernel<T, R, E, FUSED>), dim3(a.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 typedef hipError_t (*dft_launch_fn)(const DftArgs&, hipStream_t);
 
-template <class E>
+template <class E, bool FUSED>
 static dft_launch_fn find_dft_e(int table, int R)
 {
-    if (table == TABLE_3x15 && R == 12) return &launch_dft<Table3x15, 12, E>;
-    if (table == TABLE_3x15 && R == 13) return &launch_dft<Table3x15, 13, E>;
-    if (table == TABLE_1x1 && R == 12) return &launch_dft<Table1x1, 12, E>;
-    if (table == TABLE_1x1 && R == 13) return &launch_dft<Table1x1, 13, E>;
+    if (table == TABLE_3x15 && R == 12) return &launch_dft<Table3x15, 12, E, FUSED>;
+    if (table == TABLE_3x15 && R == 13) return &launch_dft<Table3x15, 13, E, FUSED>;
+    if (table == TABLE_1x1 && R == 12) return &launch_dft<Table1x1, 12, E, FUSED>;
+    if (table == TABLE_1x1 && R == 13) return &launch_dft<Table1x1, 13, E, FUSED>;
     return nullptr;
 }
 
-static dft_launch_fn find_dft(int conv, int table, int R)
+static dft_launch_fn find_dft(int conv, int table, int R, bool fused = false)
 {
-    if (conv == LENIA_CONV_DFT_SPLIT_BF16) return find_dft_e<__bf16>(table, R);
-    if (conv == LENIA_CONV_DFT_SPLIT_F16) return find_dft_e<_Float16>(table, R);
+    if (conv == LENIA_CONV_DFT_SPLIT_BF16)
+        return fused ? find_dft_e<__bf16, true>(table, R) : find_dft_e<__bf16, false>(table, R);
+    if (conv == LENIA_CONV_DFT_SPLIT_F16)
+        return fused ? find_dft_e<_Float16, true>(table, R) : find_dft_e<_Float16, false>(table, R);
     return nullptr;
 }
 
@@ -658,6 +909,27 @@ hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const
     a.tiles_x = (w.W + V - 1) / V;
     a.n_tiles = a.tiles_x * ((w.H + V - 1) / V);
     dft_launch_fn fn = find_dft(p->conv, p->table, p->R);
+    if (!fn) return hipErrorInvalidValue;
+    return fn(a, s);
+}
+
+hipError_t launch_dft_step(const lenia_plan_t p, const WorldPlan& w, const WorldArgs& wa, hipStream_t s)
+{
+    DftArgs a{};
+    a.A = wa.A;
+    a.U = nullptr;
+    a.t.f1t = w.dft_f1t;
+    a.t.f2 = w.dft_f2;
+    a.t.f3 = w.dft_f3;
+    a.t.f4t = w.dft_f4t;
+    a.t.khat = w.dft_khat;
+    a.H = w.H;
+    a.W = w.W;
+    const int V = DT - 2 * w.R;
+    a.tiles_x = (w.W + V - 1) / V;
+    a.n_tiles = a.tiles_x * ((w.H + V - 1) / V);
+    a.wd = wa;
+    dft_launch_fn fn = find_dft(p->conv, p->table, p->R, true);
     if (!fn) return hipErrorInvalidValue;
     return fn(a, s);
 }

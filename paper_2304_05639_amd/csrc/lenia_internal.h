@@ -76,8 +76,9 @@ struct Table1x1 {
 struct Table3x15 {
     static constexpr int C = 3, NK = 15, KPS = 5, KPD = 5;
     static constexpr int kidx[3][5] = {{0, 1, 2, 9, 10}, {3, 4, 5, 11, 12}, {6, 7, 8, 13, 14}};
-    // kernels by target channel, ascending
-    static constexpr int kdst[3][5] = {{0, 1, 2, 11, 13}, {3, 4, 5, 9, 14}, {6, 7, 8, 10, 12}};
+    // kernels by target channel, in the order the step sums their growth
+    // (by source channel, each channel's kernels as in kidx)
+    static constexpr int kdst[3][5] = {{0, 1, 2, 11, 13}, {9, 3, 4, 5, 14}, {10, 12, 6, 7, 8}};
     static constexpr int src[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 0, 0, 1, 1, 2, 2};
     static constexpr int dst[15] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 2, 0, 2, 0, 1};
 };

@@ -708,7 +708,10 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
             a.P_out = upd ? nP : nullptr;
             a.p_zero = zero_flags ? w.p_zero + (nP == w.ws_P ? a.n_tiles : 0) : nullptr;
             hipError_t e;
-            if (conv_is_dft(p->conv)) {
+            if (conv_is_dft(p->conv) && !saved && w.mode == MODE_LOCAL_UPDATE) {
+                // the whole step in one kernel: potentials stay on chip
+                e = launch_dft_step(p, w, a, s);
+            } else if (conv_is_dft(p->conv)) {
                 // potentials on the MFMA units into the saved buffer (or the
                 // plan's workspace), then the per-cell epilogue reads them
                 float* U = saved ? (float*)saved : w.dft_u;

@@ -28,6 +28,10 @@ struct WorldPlan;
 lenia_status build_dft_tables(lenia_plan_t p, WorldPlan& w, hipStream_t s, std::vector<void*>& keep);
 hipError_t launch_dft_potentials(const lenia_plan_t p, const WorldPlan& w, const float* A, float* U,
                                  hipStream_t s);
+// The whole step of the DFT forms in one kernel (MODE_LOCAL_UPDATE, no saved
+// potentials, alpha or flags): potentials on the MFMA units, then diffusion,
+// alpha test, growth and update of every cell of the tile.
+hipError_t launch_dft_step(const lenia_plan_t p, const WorldPlan& w, const WorldArgs& wa, hipStream_t s);
 
 // One world of a plan, with its descriptor arrays copied.
 struct WorldPlan {

@@ -228,9 +228,16 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        // growth summed per source channel, each channel's kernels in table
+        // order (the order the DFT form's fused step follows)
         if (alpha) {
 #pragma unroll
-            for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+            for (int s = 0; s < T::C; ++s)
+#pragma unroll
+                for (int j = 0; j < T::KPS; ++j) {
+                    const int k = T::kidx[s][j];
+                    sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+                }
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
@@ -244,18 +251,18 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
     } else if (mode == MODE_LOCAL_READONLY) {
 #pragma unroll
         for (int k = 0; k < NK; ++k)
-            sum[T::dst[k]] += growth(u[k], pld(plane(wd.P + (size_t)k * HW, pb), ob),
+            sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], pld(plane(wd.P + (size_t)k * HW, pb), ob),
                                      pld(plane(wd.P + (size_t)(NK + k) * HW, pb), ob),
                                      pld(plane(wd.P + (size_t)(2 * NK + k) * HW, pb), ob));
         if (wd.alpha_save) wd.alpha_save[ob >> 2] = 1;
     } else {
 #pragma unroll
-        for (int k = 0; k < NK; ++k) sum[T::dst[k]] += growth(u[k], wd.gm[k], wd.gs[k], wd.gh[k]);
+        for (int k = 0; k < NK; ++k) sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], wd.gm[k], wd.gs[k], wd.gh[k]);
         if (wd.alpha_save) wd.alpha_save[ob >> 2] = 1;
     }
 #pragma unroll
     for (int c = 0; c < T::C; ++c)
-        pst(plane(wd.A_out + (size_t)c * HW, pb), ob, clip01(a[c] + wd.dt * sum[c]));
+        pst(plane(wd.A_out + (size_t)c * HW, pb), ob, clip01(fmaf(wd.dt, sum[c], a[c])));
     if (wd.U_save) {
 #pragma unroll
         for (int k = 0; k < NK; ++k) pst(plane(wd.U_save + (size_t)k * HW, pb), ob, u[k]);
@@ -489,7 +496,7 @@ __device__ __forceinline__ void ring_epilogue_cell(const WorldArgs& wd, const fl
     }
 #pragma unroll
     for (int ch = 0; ch < T::C; ++ch)
-        pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(alpha ? a[ch] + wd.dt * sum[ch] : a[ch]));
+        pst(plane(wd.A_out + (size_t)ch * HW, pb), ob, clip01(alpha ? fmaf(wd.dt, sum[ch], a[ch]) : a[ch]));
     if (!alpha) {
 #pragma unroll
         for (int q = 0; q < NPG; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, 0.f);

@@ -128,3 +128,70 @@ def test_potentials_entry_point(L, oracle):
     A = dev(w.A)
     assert L.lib().lenia_potentials(plan.handle, A.data_ptr(), A.data_ptr(), None) == \
         L.ERR_INVALID_ARG                      # U must not alias A
+
+
+# kernel order of the fused step: per source channel, that channel's kernels
+KIDX = [0, 1, 2, 9, 10, 3, 4, 5, 11, 12, 6, 7, 8, 13, 14]
+
+
+@pytest.mark.parametrize("conv", FORMS)
+@pytest.mark.parametrize("H,W,seed,R,steps", [(64, 64, 411, 12, 1), (100, 150, 412, 12, 2),
+                                              (16, 16, 413, 12, 1), (81, 120, 414, 13, 3),
+                                              (512, 512, 415, 12, 1), (40, 200, 416, 12, 4)])
+def test_dft_fused_step_matches_two_kernel_step(L, H, W, seed, R, steps, conv):
+    """The one-kernel step (no saved buffers) and the two-kernel step
+    (potentials through HBM, then the per-cell epilogue; taken when the
+    potentials are saved) give identical bits, step after step, on worlds
+    whose tiles are ragged, smaller than the window, or wrap several times.
+    The worlds hold cells whose alpha fails at a later kernel than the first,
+    which the fused step handles by clearing genes it already wrote."""
+    import torch
+    w = inputs.test_world(H, W, seed=seed, n_blobs=max(1, H * W // 600), R=R)
+    pu = L.Plan(w, conv=conv)
+    pf = L.Plan(w, conv=conv)
+    A_u, P_u = dev(w.A), dev(w.P)
+    A_f, P_f = dev(w.A), dev(w.P)
+    late = 0
+    for t in range(steps):
+        sv = pu.new_saved()
+        A_u, P_u = pu.step(A_u, P_u, saved=sv)
+        A_f, P_f = pf.step(A_f, P_f)
+        torch.cuda.synchronize()
+        for name, x, y in (("A'", host(A_u), host(A_f)), ("P'", host(P_u), host(P_f))):
+            diff = x != y
+            assert not diff.any(), (f"{name} differs at step {t} in {int(diff.sum())} values "
+                                    f"(largest {float(np.abs(x - y).max()):.3g})")
+        u = host(pu.saved_views(sv)[0])[KIDX]
+        above = u > w.eps
+        # cells whose first potential at or below eps is not the first kernel
+        first_fail = np.argmin(above, axis=0)
+        late += int(((~above).any(axis=0) & (first_fail > 0)).sum())
+    print(f"fused vs two-kernel conv={conv} {H}x{W} R={R}: {steps} step(s) identical, "
+          f"{late} cell-steps whose alpha fails after the first kernel")
+    if H * W >= 64 * 64:        # the 16 x 16 world is one blob, uniformly alive or dead
+        assert late > 0
+
+
+@pytest.mark.parametrize("conv", FORMS)
+def test_dft_fused_multistep_against_oracle(L, oracle, conv):
+    """Three fused steps in one call against three oracle steps, each oracle
+    step starting from the GPU's previous state (teacher forcing), cells of
+    ambiguous alpha excluded."""
+    import torch
+    w = inputs.test_world(120, 136, seed=417, n_blobs=24)
+    tol_u, tol_state, tau = TOLS[conv]
+    d = oracle.Desc(w.H, w.W, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta, w.dt, 1, 1, tau=tau)
+    plan = L.Plan(w, conv=conv)
+    A, P = w.A, w.P
+    for t in range(3):
+        A1, P1 = plan.step(dev(A), dev(P))
+        torch.cuda.synchronize()
+        A1, P1 = host(A1), host(P1)
+        r = oracle.step(d, A, P)
+        ok = (r["amb"] & 1) == 0
+        check_excluded(~ok, MAX_EXCLUDED)
+        eA = float(np.abs(A1 - r["A"])[:, ok].max())
+        eP = float(np.abs(P1 - r["P"])[:, :, ok].max())
+        print(f"fused conv={conv} t={t}: A' err {eA:.2e}  P' err {eP:.2e}")
+        assert eA <= tol_state and eP <= tol_state
+        A, P = A1, P1
