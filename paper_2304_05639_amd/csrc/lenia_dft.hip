@@ -630,33 +630,34 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 asm volatile("" : "+v"(tid));
 #pragma unroll
                 for (int r = 0; r < NCR; ++r) {
-                    if (dead_at[r] < 0) continue;
-                    const int ci = tid + 256 * r;
+                    // branch-free: every slot runs the same instructions, and
+                    // the selects keep what alpha allows.  A slot past the
+                    // tile's cells reads cell 0; off the world (dead_at < 0)
+                    // the store offset lies past the plane, so the buffer
+                    // store is dropped.
+                    const int ci0 = tid + 256 * r;
+                    const int ci = (256 * r + 255 < V * V || ci0 < V * V) ? ci0 : 0;
                     const int p = ci / V, q = ci - (ci / V) * V;
-                    float pd0 = 0.f, pd1 = 0.f, pd2 = 0.f;
-                    if (dead_at[r] == kAlive) {
-                        const float u = ut[ci];
-                        bool alive = u > eps;
-                        if (alive) {
-                            const int c = (p + 1) * HS + q + 1;
-                            pd0 = diffuse_staged(gst, c, HS, cs, ncs);
-                            pd1 = diffuse_staged(gst + GSLOT, c, HS, cs, ncs);
-                            pd2 = diffuse_staged(gst + 2 * GSLOT, c, HS, cs, ncs);
-                            alive = (pd0 > eps) && (pd1 > eps) && (pd2 > eps);
-                        }
-                        if (alive) {
+                    const bool live = dead_at[r] == kAlive;
+                    const float u = ut[ci];
+                    const int c = (p + 1) * HS + q + 1;
+                    const float pd0 = diffuse_staged(gst, c, HS, cs, ncs);
+                    const float pd1 = diffuse_staged(gst + GSLOT, c, HS, cs, ncs);
+                    const float pd2 = diffuse_staged(gst + 2 * GSLOT, c, HS, cs, ncs);
+                    const bool ok = live && (u > eps) && (pd0 > eps) && (pd1 > eps) && (pd2 > eps);
+                    float cur = gsum[r][0];
 #pragma unroll
-                            for (int c = 0; c < T::C; ++c)
-                                if (c == dk) gsum[r][c] = growth_acc(gsum[r][c], u, pd0, pd1, pd2);
-                        } else {
-                            dead_at[r] = pos;
-                            pd0 = pd1 = pd2 = 0.f;
-                        }
-                    }
-                    const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
-                    pst_stream(o0, ob, pd0);
-                    pst_stream(o1, ob, pd1);
-                    pst_stream(o2, ob, pd2);
+                    for (int c3 = 1; c3 < T::C; ++c3) cur = (c3 == dk) ? gsum[r][c3] : cur;
+                    const float gacc = growth_acc(cur, u, pd0, pd1, pd2);
+#pragma unroll
+                    for (int c3 = 0; c3 < T::C; ++c3)
+                        gsum[r][c3] = (ok && c3 == dk) ? gacc : gsum[r][c3];
+                    dead_at[r] = (live && !ok) ? pos : dead_at[r];
+                    const uint32_t ob = (dead_at[r] >= 0)
+                        ? 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q)) : 0xFFFFFFF0u;
+                    pst_stream(o0, ob, ok ? pd0 : 0.f);
+                    pst_stream(o1, ob, ok ? pd1 : 0.f);
+                    pst_stream(o2, ob, ok ? pd2 : 0.f);
                     // one cell at a time: hoisting every cell's 15 LDS reads
                     // ahead would take more registers than the wave has
                     __builtin_amdgcn_sched_barrier(0);
