@@ -217,6 +217,14 @@ __device__ __forceinline__ void dma_barrier()
     asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// The same, leaving this wave's N newest vector-memory operations (the next
+// kernel's gene DMA) in flight.
+template <int N>
+__device__ __forceinline__ void dma_barrier_keep()
+{
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_waitcnt lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
 // Gene diffusion of one cell from a staged plane (side hs, the cell at c):
 // the disk values in the epilogue's order up, left, centre, right, down.
 __device__ __forceinline__ float diffuse_staged(const float* g, int c, int hs, float cs, float ncs)
@@ -254,30 +262,36 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
     // being processed (fp32), plus a scratch region shared by the forward
     // stages (Xs, Yt) and the inverse stages (the split spectral product Ust
     // and Zc, which do not overlap each other)
-    constexpr int FWD_E = 2 * DT * XS_P + 2 * NB * YT_P;
-    constexpr int INV_E = 2 * NB * UST_P + 2 * ZC_ROWS * ZC_P;
-    constexpr int SCRATCH_E = (FWD_E > INV_E) ? FWD_E : INV_E;
-    __shared__ __attribute__((aligned(16))) float th[NB * TH_P];
-    __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
-    __shared__ float wmax[4];
-    // fused step: the staged gene planes (side V + 2, whole DMA rounds of the
-    // four waves per plane) and u_k of the current kernel, which takes the
-    // place of Ust once GEMM3 has read it
+    //
+    // The fused step also stages gene planes (below) in two buffers, so that
+    // the next kernel's planes load while this one's are used; to fit two
+    // workgroups per CU it overlays more of the scratch: Yt on Xs (GEMM1 keeps
+    // its results in registers across a barrier), and Zc on Ust (likewise
+    // GEMM3), with u_k of the current kernel after Zc.
     constexpr int HS = V + 2;
     constexpr int NGI = (HS * HS + 255) / 256;      // DMA instructions per wave and plane
     constexpr int GSLOT = 256 * NGI;
     constexpr int NCR = (V * V + 255) / 256;        // cells per thread
-    static_assert(V * V * 4 <= 2 * NB * UST_P * (int)sizeof(E), "u_k must fit in Ust");
-    __shared__ __attribute__((aligned(16))) float gst[FUSED ? 3 * GSLOT : 1];
-    float* ut = (float*)scr;
+    constexpr int XS_E = 2 * DT * XS_P, YT_E = 2 * NB * YT_P, UST_E = 2 * NB * UST_P;
+    constexpr int ZC_E = 2 * ZC_ROWS * ZC_P, UT_E = V * V * 4 / (int)sizeof(E);
+    constexpr int FWD_E = FUSED ? (XS_E > YT_E ? XS_E : YT_E) : XS_E + YT_E;
+    constexpr int INV_E = FUSED ? ((ZC_E + UT_E > UST_E) ? ZC_E + UT_E : UST_E) : UST_E + ZC_E;
+    constexpr int SCRATCH_E = (FWD_E > INV_E) ? FWD_E : INV_E;
+    static_assert(FUSED || V * V * 4 <= UST_E * (int)sizeof(E), "u_k must fit in Ust");
+    __shared__ __attribute__((aligned(16))) float th[NB * TH_P];
+    __shared__ __attribute__((aligned(16))) E scr[SCRATCH_E];
+    __shared__ float wmax[4];
+    __shared__ __attribute__((aligned(16))) float gstA[FUSED ? 3 * GSLOT : 1];
+    __shared__ __attribute__((aligned(16))) float gstB[FUSED ? 3 * GSLOT : 1];
     E* xs_hi = scr;
     E* xs_lo = scr + DT * XS_P;
-    E* yt_hi = scr + 2 * DT * XS_P;
+    E* yt_hi = FUSED ? scr : scr + XS_E;
     E* yt_lo = yt_hi + NB * YT_P;
     E* ust_hi = scr;
     E* ust_lo = scr + NB * UST_P;
-    E* zc_hi = scr + 2 * NB * UST_P;
+    E* zc_hi = FUSED ? scr : scr + UST_E;
     E* zc_lo = zc_hi + ZC_ROWS * ZC_P;
+    float* ut = FUSED ? (float*)(scr + ZC_E) : (float*)scr;
 
     const int H = g.H, W = g.W;
     const size_t HW = (size_t)H * W;
@@ -369,6 +383,22 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
         }
     }
 
+    // gene planes kk, NK + kk, 2 NK + kk (m, s, h of kernel kk) into a staging
+    // buffer by direct-to-LDS loads; the buffers are distinct arrays, so that
+    // the compiler's own waits before reading one do not wait for the other's
+    auto stage_genes = [&](int kk, float* gb) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const plane_t pl = plane(wd.P + (size_t)(q * T::NK + kk) * HW, pb);
+#pragma unroll
+            for (int i = 0; i < NGI; ++i)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    pl, (__attribute__((address_space(3))) void*)(gb + q * GSLOT + 256 * i + 64 * wave), 4,
+                    (int)goff[i], 0, 0, 0);
+        }
+    };
+    if constexpr (FUSED) stage_genes(T::kidx[0][0], gstA);
+
     // ---- per source channel: forward transform, then its kernels ------------
 #pragma unroll 1
     for (int s = 0; s < T::C; ++s) {
@@ -432,6 +462,7 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 #pragma unroll
                 for (int n = 0; n < 4; ++n) acc[n] = mma3<E>(ah, al, bh[n], bl[n], acc[n]);
             }
+            if constexpr (FUSED) lds_barrier();    // every wave has read Xs, which Yt overlays
             // Y column c = 16n + lr, rows i = 16w + ld + j  ->  Yt[c % 32][64 (c / 32) + i]
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
@@ -487,18 +518,6 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
         for (int j = 0; j < T::KPS; ++j) {
             const int k = T::kidx[s][j];
             const float* kh = g.t.khat + (size_t)k * (NB + 1) * DT;
-            if constexpr (FUSED) {
-                // stage gene planes k, NK + k, 2 NK + k (m, s, h of kernel k)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const plane_t pl = plane(wd.P + (size_t)(q * T::NK + k) * HW, pb);
-#pragma unroll
-                    for (int i = 0; i < NGI; ++i)
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            pl, (__attribute__((address_space(3))) void*)(gst + q * GSLOT + 256 * i + 64 * wave),
-                            4, (int)goff[i], 0, 0, 0);
-                }
-            }
             // the spectral product U = Xh * Khat_k, split into LDS once for
             // all waves: real part at column a, imaginary part at 64 + a
             {
@@ -540,6 +559,17 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 *(ev8*)(ust_hi + sp_b * UST_P + DT + sp_a8) = uh;
                 *(ev8*)(ust_lo + sp_b * UST_P + DT + sp_a8) = ul;
             }
+            // the next kernel's genes load while this one is transformed and
+            // its cells computed (issued after the spectra are read, so that
+            // no wait for those loads waits for the DMA too)
+            const int pos = s * T::KPS + j;
+            if constexpr (FUSED) {
+                if (pos + 1 < T::NK) {
+                    const int kn = T::kidx[(pos + 1) / T::KPS][(pos + 1) % T::KPS];
+                    if ((pos + 1) & 1) stage_genes(kn, gstB);
+                    else stage_genes(kn, gstA);
+                }
+            }
             lds_barrier();    // Ust is complete; the previous GEMM4 is done with Zc
             // GEMM3: Z^T (32 x 80) = Ust^T (32 x 128) F3^T
             {
@@ -557,6 +587,7 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                         if (m == wave) acc4 = mma3<E>(ah, al, b3h[1][ks], b3l[1][ks], acc4);
                     }
                 }
+                if constexpr (FUSED) lds_barrier();    // every wave has read Ust, which Zc overlays
                 // Z^T row b = 16m + ld + j, column p' = 16 nt + lr -> Zc[p' mod V][32 (p' >= V) + b]
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -616,8 +647,8 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 // diffusion, alpha test and growth of kernel k at this
                 // thread's cells, from u_k and the staged genes; the new gene
                 // values go out now (0 where alpha has failed)
-                dma_barrier();
-                const int pos = s * T::KPS + j;
+                if (pos + 1 < T::NK) dma_barrier_keep<3 * NGI>();
+                else dma_barrier();
                 const int dk = T::dst[k];
                 const float eps = wd.eps, cs = wd.cnt_scale, ncs = wd.cnt_bias;
                 const plane_t o0 = plane(wd.P_out + (size_t)k * HW, pb);
@@ -628,6 +659,8 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 // transforms need)
                 int tid = threadIdx.x;
                 asm volatile("" : "+v"(tid));
+                // the current kernel's genes are in buffer pos & 1
+                auto cells = [&](const float* gb) {
 #pragma unroll
                 for (int r = 0; r < NCR; ++r) {
                     // branch-free: every slot runs the same instructions, and
@@ -641,9 +674,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                     const bool live = dead_at[r] == kAlive;
                     const float u = ut[ci];
                     const int c = (p + 1) * HS + q + 1;
-                    const float pd0 = diffuse_staged(gst, c, HS, cs, ncs);
-                    const float pd1 = diffuse_staged(gst + GSLOT, c, HS, cs, ncs);
-                    const float pd2 = diffuse_staged(gst + 2 * GSLOT, c, HS, cs, ncs);
+                    const float pd0 = diffuse_staged(gb, c, HS, cs, ncs);
+                    const float pd1 = diffuse_staged(gb + GSLOT, c, HS, cs, ncs);
+                    const float pd2 = diffuse_staged(gb + 2 * GSLOT, c, HS, cs, ncs);
                     const bool ok = live && (u > eps) && (pd0 > eps) && (pd1 > eps) && (pd2 > eps);
                     float cur = gsum[r][0];
 #pragma unroll
@@ -662,6 +695,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                     // ahead would take more registers than the wave has
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                };
+                if (pos & 1) cells(gstB);
+                else cells(gstA);
                 lds_barrier();    // u_k and the staged genes are free again
             }
         }
