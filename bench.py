@@ -51,11 +51,14 @@ LEG_SRCS = {
     "ring": ("lenia_step.hip", "lenia_device.h", "lenia_internal.h", "lenia_plan.cpp"),
     "batched": ("lenia_step.hip", "lenia_device.h", "lenia_internal.h", "lenia_plan.cpp"),
     "dft_f16": ("lenia_dft.hip", "lenia_device.h", "lenia_internal.h"),
+    "dft_f16_step": ("lenia_dft.hip", "lenia_device.h", "lenia_internal.h", "lenia_plan.cpp"),
 }
 # the kernel each leg's roofline is about (a substring of its name in the trace)
 LEG_KERNEL = {"headline": "step_kernel<lenia::Table3x15, 12, 8, 32>",
               "ring": "ring_step_kernel", "batched": "step_batch_kernel",
-              "dft_f16": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_Lb1E"}   # the fused step, as traced
+              # as the trace names them: potentials only, and the whole (fused) step
+              "dft_f16": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_Lb0E",
+              "dft_f16_step": "15dft_conv_kernelINS_9Table3x15ELi12EDF16_Lb1E"}
 
 
 def sources_sha(names) -> str:
@@ -270,10 +273,11 @@ MFMA_FLOPS = 16 * 16 * 32 * 2
 
 
 def dft_form(world, A, P, conv: int, steps: int = 20, warmup: int = 5, pot_reps: int = 20):
-    """A split DFT-as-GEMM form from the headline's state: full-step throughput
-    (the step is one kernel, the potentials never leave the chip) against the
-    dense MFMA peak of its operand type (2.5 PFLOP/s for bf16 and fp16), and the
-    potentials-only kernel (lenia_potentials) timed alone."""
+    """A split DFT-as-GEMM form from the headline's state.  `roofline` is the
+    potentials-only MFMA kernel (lenia_potentials, timed alone) against the
+    dense MFMA peak of its operand type (2.5 PFLOP/s for bf16 and fp16);
+    `value` and `fused_step` are the whole step, one kernel in which the
+    potentials never leave the chip."""
     import torch
     from paper_2304_05639_amd import lenia
     plan = lenia.Plan(world, conv=conv)
@@ -293,16 +297,21 @@ def dft_form(world, A, P, conv: int, steps: int = 20, warmup: int = 5, pot_reps:
     _, s_ms = timed(lambda: st.step(plan, steps))
     s_ms /= steps
     flops = n_tiles * DFT_MFMA_PER_TILE * MFMA_FLOPS
-    achieved = flops / (s_ms / 1e3) / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / BF16_PEAK_TFLOPS, "kernel": "dft_conv_kernel (whole step, fused)",
-            "kernel_ms": s_ms, "traffic": None}
+    pot = flops / (k_ms / 1e3) / 1e12
+    roof = {"bound": "mfma", "achieved": pot, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": pot / BF16_PEAK_TFLOPS, "kernel": "dft_conv_kernel (potentials only)",
+            "kernel_ms": k_ms, "traffic": None}
+    step = {"kernel": "dft_conv_kernel (whole step, fused)", "ms": s_ms,
+            "mfma_tflops": flops / (s_ms / 1e3) / 1e12,
+            "mfma_frac": flops / (s_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+            "hbm_gbs_algorithmic": BYTES_PER_CELL * world.H * world.W / (s_ms / 1e3) / 1e9,
+            "traffic": None}
     if conv == lenia.CONV_DFT_SPLIT_F16:
-        roof["traffic"] = counter_traffic("dft_f16", {"warmup": warmup, "steps": steps})
-    pot_tflops = flops / (k_ms / 1e3) / 1e12
+        roof["traffic"] = counter_traffic("dft_f16", {"reps": pot_reps})
+        step["traffic"] = counter_traffic("dft_f16_step", {"warmup": warmup, "steps": steps})
     return {"value": world.H * world.W / (s_ms / 1e3), "unit": "cell-updates/s",
             "ms_per_step": s_ms, "alive_frac_end": alive(st.P), "roofline": roof,
-            "potentials_kernel": {"ms": k_ms, "tflops": pot_tflops, "frac": pot_tflops / BF16_PEAK_TFLOPS},
+            "fused_step": step,
             "note": f"{n_tiles} tiles of 64x64 (valid {V}x{V}), {DFT_MFMA_PER_TILE} MFMA per tile; "
                     f"timed from the headline's state"}
 
@@ -563,7 +572,7 @@ def main():
         leg, cg, out_json = args.counter_summary
         K, W = args.steps, args.warmup
         first, count = {"headline": (ADVANCE + W, K), "ring": (RING_ADVANCE + W, K),
-                        "dft_f16": (-20, 20), "batched": (-500, 500)}[leg]
+                        "dft_f16": (2, 20), "dft_f16_step": (-20, 20), "batched": (-500, 500)}[leg]
         rows = _counter_rows(cg)
         names = sorted({r["Counter_Name"] for r in rows})
         res = {"leg": leg, "kernel": LEG_KERNEL[leg], "counters": {}}
@@ -585,7 +594,8 @@ def main():
         windows = {"headline": ({"advance": ADVANCE, "warmup": W, "steps": K}, ADVANCE + W, K),
                    "ring": ({"advance": RING_ADVANCE, "warmup": W, "steps": K}, RING_ADVANCE + W, K),
                    "batched": ({"steps": 500}, -500, 500),
-                   "dft_f16": ({"warmup": 5, "steps": 20}, -20, 20)}
+                   "dft_f16": ({"reps": 20}, 2, 20),
+                   "dft_f16_step": ({"warmup": W, "steps": K}, -20, 20)}
         window, first, count = windows[leg]
         summarize(leg, fg, wg, window, first, count, args.command)
         return
