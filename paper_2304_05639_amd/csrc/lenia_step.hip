@@ -441,58 +441,67 @@ __device__ __forceinline__ void ring_epilogue_cell(const WorldArgs& wd, const fl
     float sum[T::C];
 #pragma unroll
     for (int ch = 0; ch < T::C; ++ch) sum[ch] = 0.f;
+    // The 9 genes of each kernel are read as 3 groups of 3 planes (their r = 1
+    // disks), 45 groups in all, kernels in table order.  Two groups are kept
+    // in flight ahead of the one being reduced, across kernel boundaries too,
+    // so that the loads of the next kernel's genes run under this kernel's
+    // ring weights (48 exponentials).  Group 3 j + i lives in buffer i.
+    auto kernel_at = [](int pos) { return T::kidx[pos / T::KPS][pos % T::KPS]; };
+    auto load_group = [&](float (&v)[3][5], int pos, int grp) {
+        const int kk = kernel_at(pos);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) load_disk(v[i], plane(wd.P + (size_t)((grp * 3 + i) * NK + kk) * HW, pb), nb);
+    };
+    float v[3][3][5];
+    load_group(v[0], 0, 0);
+    load_group(v[1], 0, 1);
 #pragma unroll
     for (int c = 0; c < T::C; ++c) {
 #pragma unroll 1
-        for (int j = 0; j < T::KPS; ++j) {
-            if (!alpha) continue;
-            const int k = T::kidx[c][j];
-            // the kernel's 9 genes, diffused (Section 2.3), in groups of three
-            // planes with the next group's reads in flight
-            float g[9];
-            float v[2][3][5];
+      for (int j = 0; j < T::KPS; ++j) {
+        // a wave whose cells have all lost alpha stops reading
+        if (!__any(alpha)) continue;
+        const int pos = c * T::KPS + j;
+        const int k = T::kidx[c][j];
+        // stores of a cell whose alpha has failed go past the plane (dropped)
+        float g[9];
 #pragma unroll
-            for (int i = 0; i < 3; ++i) load_disk(v[0][i], plane(wd.P + (size_t)(i * NK + k) * HW, pb), nb);
+        for (int grp = 0; grp < 3; ++grp) {
+            // issue the group two ahead: this kernel's third, or the next
+            // kernel's first or second
+            if (grp == 0) load_group(v[2], pos, 2);
+            else if (pos + 1 < NK) load_group(v[grp - 1], pos + 1, grp - 1);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int grp = 0; grp < 3; ++grp) {
-                if (grp + 1 < 3) {
-#pragma unroll
-                    for (int i = 0; i < 3; ++i)
-                        load_disk(v[(grp + 1) & 1][i],
-                                  plane(wd.P + (size_t)(((grp + 1) * 3 + i) * NK + k) * HW, pb), nb);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const int q = grp * 3 + i;
-                    g[q] = diffuse_disk(v[grp & 1][i], cs, ncs);
-                    alpha = alpha && (g[q] > eps);
-                    pst_stream(plane(wd.P_out + (size_t)(q * NK + k) * HW, pb), ob, g[q]);
-                }
-                __builtin_amdgcn_sched_barrier(0);
+            for (int i = 0; i < 3; ++i) {
+                const int q = grp * 3 + i;
+                g[q] = diffuse_disk(v[grp][i], cs, ncs);
+                alpha = alpha && (g[q] > eps);
+                pst_stream(plane(wd.P_out + (size_t)(q * NK + k) * HW, pb), alpha ? ob : 0xFFFFFFF0u, g[q]);
             }
-            if (!alpha) continue;
-            // ring weights of the two bumps: b exp2(c (x - r)^2), c = -log2(e) / (2 w^2)
-            const float c1 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[1] * g[1]);
-            const float c2 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[4] * g[4]);
-            float num = 0.f, den = 0.f;
-#pragma unroll
-            for (int sl = 0; sl < NRE; ++sl) {
-                constexpr float inv_nr = 1.0f / (float)NR;
-                const float x = (float)kRings<R>.ring_of_slot[sl] * inv_nr;
-                const float d1 = x - g[0], d2 = x - g[3];
-                const float kw = g[2] * __builtin_amdgcn_exp2f(c1 * (d1 * d1)) +
-                                 g[5] * __builtin_amdgcn_exp2f(c2 * (d2 * d2));
-                num = fmaf(kw, S[sl][c], num);
-                den = fmaf(kw, (float)kRings<R>.size_of_slot[sl], den);
-            }
-            const float u = (den > 0.f) ? num / den : 0.f;
-            alpha = alpha && (u > eps);
-            const float gk = growth(u, g[6], g[7], g[8]);
-            const int dk = T::dst[k];
-#pragma unroll
-            for (int ch = 0; ch < T::C; ++ch) sum[ch] += (dk == ch) ? gk : 0.f;
+            __builtin_amdgcn_sched_barrier(0);
         }
+        // ring weights of the two bumps: b exp2(c (x - r)^2), c = -log2(e) / (2 w^2)
+        const float c1 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[1] * g[1]);
+        const float c2 = -0.72134752044448170f * __builtin_amdgcn_rcpf(g[4] * g[4]);
+        float num = 0.f, den = 0.f;
+#pragma unroll
+        for (int sl = 0; sl < NRE; ++sl) {
+            constexpr float inv_nr = 1.0f / (float)NR;
+            const float x = (float)kRings<R>.ring_of_slot[sl] * inv_nr;
+            const float d1 = x - g[0], d2 = x - g[3];
+            const float kw = g[2] * __builtin_amdgcn_exp2f(c1 * (d1 * d1)) +
+                             g[5] * __builtin_amdgcn_exp2f(c2 * (d2 * d2));
+            num = fmaf(kw, S[sl][c], num);
+            den = fmaf(kw, (float)kRings<R>.size_of_slot[sl], den);
+        }
+        const float u = (den > 0.f) ? num / den : 0.f;
+        alpha = alpha && (u > eps);
+        const float gk = growth(u, g[6], g[7], g[8]);
+        const int dk = T::dst[k];
+#pragma unroll
+        for (int ch = 0; ch < T::C; ++ch) sum[ch] += (alpha && dk == ch) ? gk : 0.f;
+      }
     }
 #pragma unroll
     for (int ch = 0; ch < T::C; ++ch)
