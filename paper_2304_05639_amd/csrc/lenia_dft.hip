@@ -109,9 +109,9 @@ constexpr int DT = 64;                   // DFT tile
 constexpr int DT2 = 128;                 // real-embedded complex dimension of a full axis
 constexpr int NB = 32;                   // half-spectrum columns (0 and 32 packed in column 0)
 constexpr int XS_P = DT + 8;             // LDS row pitches (operand-type / fp32 elements)
-constexpr int YT_P = DT2 + 8;
+constexpr int YT_P = DT2 + 16;
 constexpr int TH_P = DT2 + 4;
-constexpr int UST_P = DT2 + 8;
+constexpr int UST_P = DT2 + 16;
 constexpr int ZC_P = DT + 8;
 constexpr int ZC_ROWS = 48;              // GEMM4 rows (V <= 48)
 constexpr int F3_ROWS = 80;              // GEMM3 columns (2V <= 80)
