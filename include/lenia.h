@@ -133,6 +133,20 @@ typedef struct {
                                    assume finite inputs and do not check them
                                    otherwise (a NaN fails every comparison and
                                    the clips pass it on).                        */
+#define LENIA_FLAG_DFT_FUSED 4u
+                                /* DFT forms: run every step that can be fused
+                                   (localized genes updated each step, no saved
+                                   buffer) as one kernel, whatever the world's
+                                   size.  By default a plan fuses only when the
+                                   world has at least 4 DFT tiles per compute
+                                   unit: below that the one-kernel step's few
+                                   workgroups run the 15 kernels' transforms one
+                                   after another, and the two-kernel step (the
+                                   potentials, then a per-cell epilogue spread
+                                   over the whole GPU) is faster (at 256^2, 57
+                                   against 104 us per step).  Both give
+                                   identical results.  Ignored by the direct and
+                                   ring forms.                                   */
 
 typedef struct lenia_plan_* lenia_plan_t;
 

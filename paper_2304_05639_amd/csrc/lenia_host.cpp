@@ -202,7 +202,7 @@ lenia_status validate(const lenia_desc* d)
         return fail(LENIA_ERR_INVALID_ARG, "unknown conv form");
     if ((d->tile_y == 0) != (d->tile_x == 0) || d->tile_y < 0 || d->tile_x < 0)
         return fail(LENIA_ERR_INVALID_ARG, "tile_y and tile_x must both be 0 or both > 0");
-    if (d->flags & ~(LENIA_FLAG_AUTOTUNE | LENIA_FLAG_CHECK_FINITE))
+    if (d->flags & ~(LENIA_FLAG_AUTOTUNE | LENIA_FLAG_CHECK_FINITE | LENIA_FLAG_DFT_FUSED))
         return fail(LENIA_ERR_INVALID_ARG, "unknown flags");
     if (rings && !(d->localized && d->genotype_update))
         return fail(LENIA_ERR_INVALID_ARG, "ring-decomposed kernels need localized genes with "

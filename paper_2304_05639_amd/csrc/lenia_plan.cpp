@@ -503,8 +503,18 @@ static lenia_status make_plan(const lenia_desc* ds, int n, void* stream, lenia_p
     std::vector<void*> keep;
     lenia_status st = LENIA_OK;
     for (int i = 0; i < n && st == LENIA_OK; ++i) st = build_world(p, &ds[i], p->worlds[i], s, keep);
-    if (st == LENIA_OK && conv_is_dft(p->conv))
+    if (st == LENIA_OK && conv_is_dft(p->conv)) {
         st = build_dft_tables(p, p->worlds[0], s, keep);
+        // one kernel per step once the world fills the GPU several times over
+        // (LENIA_FLAG_DFT_FUSED: always)
+        WorldPlan& w0 = p->worlds[0];
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+            cus = 0;
+        const int v = dft_valid_side(w0.R);
+        const long tiles = (long)((w0.H + v - 1) / v) * (long)((w0.W + v - 1) / v);
+        w0.dft_fused = (ds[0].flags & LENIA_FLAG_DFT_FUSED) || (cus > 0 && tiles >= 4L * cus);
+    }
     for (int i = 0; i < n; ++i)
         if (ds[i].flags & LENIA_FLAG_CHECK_FINITE) p->check_finite = true;
     if (st == LENIA_OK && p->check_finite)
@@ -708,7 +718,7 @@ lenia_status lenia_step(lenia_plan_t p, const float* A_in, const float* P_in, fl
             a.P_out = upd ? nP : nullptr;
             a.p_zero = zero_flags ? w.p_zero + (nP == w.ws_P ? a.n_tiles : 0) : nullptr;
             hipError_t e;
-            if (conv_is_dft(p->conv) && !saved && w.mode == MODE_LOCAL_UPDATE) {
+            if (conv_is_dft(p->conv) && !saved && w.mode == MODE_LOCAL_UPDATE && w.dft_fused) {
                 // the whole step in one kernel: potentials stay on chip
                 e = launch_dft_step(p, w, a, s);
             } else if (conv_is_dft(p->conv)) {

@@ -54,6 +54,7 @@ struct WorldPlan {
     void* dft_f4t = nullptr;
     float* dft_khat = nullptr;
     float* dft_u = nullptr;        // [NK][H][W]
+    bool dft_fused = false;        // DFT forms: eligible steps run as one kernel
     float* ws_A = nullptr;         // ping-pong state workspace [C][H][W]
     float* ws_P = nullptr;         // [gene_types][NK][H][W] (gene update only)
     uint8_t* p_zero = nullptr;     // [2][tiles] zero-gene tile flags of the caller's P

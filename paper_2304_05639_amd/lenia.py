@@ -20,6 +20,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OUT_OF_MEMORY, ERR_HIP, ERR_STATE, ERR
 CONV_AUTO, CONV_DIRECT_F32, CONV_DFT_SPLIT_BF16, CONV_DFT_SPLIT_F16 = range(4)
 FLAG_AUTOTUNE = 1
 FLAG_CHECK_FINITE = 2
+FLAG_DFT_FUSED = 4
 
 API = ("lenia_desc_validate", "lenia_kernel_taps", "lenia_plan", "lenia_plan_batched",
        "lenia_step", "lenia_step_batched", "lenia_potentials", "lenia_saved_bytes", "lenia_backward",
@@ -131,7 +132,7 @@ class DescBuilder:
     lenia_desc and keeps the host arrays alive."""
 
     def __init__(self, w, conv: int = CONV_AUTO, tile: Optional[Sequence[int]] = None,
-                 autotune: bool = False, check_finite: bool = False):
+                 autotune: bool = False, check_finite: bool = False, dft_fused: bool = False):
         nk = int(w.n_kernels)
         self._src = np.ascontiguousarray(w.src, np.int32)
         self._dst = np.ascontiguousarray(w.dst, np.int32)
@@ -149,7 +150,8 @@ class DescBuilder:
                          int(w.genotype_update), dp(self._m), dp(self._s), dp(self._h),
                          float(w.eps), int(w.r_diff), int(conv), int(ty), int(tx),
                          (FLAG_AUTOTUNE if autotune else 0) |
-                         (FLAG_CHECK_FINITE if check_finite else 0), int(getattr(w, "n_ring", 0)))
+                         (FLAG_CHECK_FINITE if check_finite else 0) |
+                         (FLAG_DFT_FUSED if dft_fused else 0), int(getattr(w, "n_ring", 0)))
 
 
 def validate(w, **kw) -> int:
@@ -196,9 +198,9 @@ class Plan:
     """A single-world plan (lenia_plan)."""
 
     def __init__(self, world, conv: int = CONV_AUTO, tile=None, autotune: bool = False,
-                 stream=None, check_finite: bool = False):
+                 stream=None, check_finite: bool = False, dft_fused: bool = False):
         self.world = world
-        self._b = DescBuilder(world, conv, tile, autotune, check_finite)
+        self._b = DescBuilder(world, conv, tile, autotune, check_finite, dft_fused)
         h = C.c_void_p()
         _check(lib().lenia_plan(C.byref(self._b.desc), C.c_void_p(_stream(stream)), C.byref(h)),
                "lenia_plan")

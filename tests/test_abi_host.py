@@ -114,8 +114,18 @@ def test_check_finite_flag_validates():
     assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
     b.desc.flags = L.FLAG_CHECK_FINITE | L.FLAG_AUTOTUNE
     assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
-    b.desc.flags = L.FLAG_CHECK_FINITE | 4
+    b.desc.flags = L.FLAG_CHECK_FINITE | 8
     assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.ERR_INVALID_ARG
+
+
+def test_dft_fused_flag_validates():
+    import ctypes
+    w = inputs.test_world(32, 32, seed=2, n_blobs=1)
+    b = L.DescBuilder(w, conv=L.CONV_DFT_SPLIT_F16, dft_fused=True)
+    assert b.desc.flags == L.FLAG_DFT_FUSED
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
+    b.desc.flags = L.FLAG_DFT_FUSED | L.FLAG_CHECK_FINITE | L.FLAG_AUTOTUNE
+    assert L.lib().lenia_desc_validate(ctypes.byref(b.desc)) == L.OK
 
 
 def test_null_descriptor_rejected():

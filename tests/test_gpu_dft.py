@@ -148,7 +148,7 @@ def test_dft_fused_step_matches_two_kernel_step(L, H, W, seed, R, steps, conv):
     import torch
     w = inputs.test_world(H, W, seed=seed, n_blobs=max(1, H * W // 600), R=R)
     pu = L.Plan(w, conv=conv)
-    pf = L.Plan(w, conv=conv)
+    pf = L.Plan(w, conv=conv, dft_fused=True)
     A_u, P_u = dev(w.A), dev(w.P)
     A_f, P_f = dev(w.A), dev(w.P)
     late = 0
@@ -181,7 +181,7 @@ def test_dft_fused_multistep_against_oracle(L, oracle, conv):
     w = inputs.test_world(120, 136, seed=417, n_blobs=24)
     tol_u, tol_state, tau = TOLS[conv]
     d = oracle.Desc(w.H, w.W, 3, 15, w.src, w.dst, w.R, w.n_shells, w.beta, w.dt, 1, 1, tau=tau)
-    plan = L.Plan(w, conv=conv)
+    plan = L.Plan(w, conv=conv, dft_fused=True)
     A, P = w.A, w.P
     for t in range(3):
         A1, P1 = plan.step(dev(A), dev(P))
