@@ -175,7 +175,7 @@ __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ 
 // Gene diffusion, alpha mask, growth and update of one cell (gy, gx) given its
 // potentials u and its current state a[c]; writes A' and P' (and the saved
 // potentials / alpha when requested).
-template <class T>
+template <class T, bool KMAJOR = true>
 __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, const float (&u)[T::NK],
                                               const float (&a)[T::C], int gy, int gx)
 {
@@ -198,49 +198,97 @@ __device__ __forceinline__ void epilogue_cell(const WorldArgs& wd, int mode, con
         bool alpha = true;
 #pragma unroll
         for (int k = 0; k < NK; ++k) alpha = alpha && (u[k] > eps);
-        float pd[NP];
-        if (alpha) {
-            // diffuse every gene plane (Section 2.3) and test it against the
-            // cutoff.  The disks are read in groups of G planes, the next
-            // group's reads issued before the current group is reduced, so a
-            // wave has one round trip in flight rather than one per plane (the
-            // scheduling barriers keep the compiler from serialising them again).
-            constexpr int G = (NP % LENIA_GENE_GROUP == 0) ? LENIA_GENE_GROUP : 3, NG = NP / G;
-            static_assert(NP % G == 0, "gene planes come in threes");
-            const NbrB nb = neighbour_bytes(gy, gx, H, W);
-            const float cs = wd.cnt_scale, ncs = wd.cnt_bias;
-            float v[2][G][5];
+        if constexpr (KMAJOR) {
+            if (alpha) {
+                // diffuse every gene plane (Section 2.3), kernel by kernel in table
+                // order: kernel k's m, s and h disks (planes k, NK + k, 2 NK + k)
+                // are read together, two kernels' reads in flight ahead of the
+                // one being reduced (the scheduling barriers keep the compiler
+                // from serialising them).  Each kernel's diffused genes are tested
+                // against the cutoff, written out while alpha holds, and enter
+                // its growth at once, so no diffused plane stays live; a cell
+                // whose alpha fails gets all its genes written as 0 below.
+                const NbrB nb = neighbour_bytes(gy, gx, H, W);
+                const float cs = wd.cnt_scale, ncs = wd.cnt_bias;
+                auto load_kernel = [&](float (&vv)[3][5], int pos) {
+                    const int kk = T::kidx[pos / T::KPS][pos % T::KPS];
 #pragma unroll
-            for (int i = 0; i < G; ++i) load_disk(v[0][i], plane(wd.P + (size_t)i * HW, pb), nb);
+                    for (int p = 0; p < 3; ++p) load_disk(vv[p], plane(wd.P + (size_t)(p * NK + kk) * HW, pb), nb);
+                };
+                float v[3][3][5];
+                load_kernel(v[0], 0);
+                if (NK > 1) load_kernel(v[1], 1);
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-                if (g + 1 < NG) {
-#pragma unroll
-                    for (int i = 0; i < G; ++i)
-                        load_disk(v[(g + 1) & 1][i], plane(wd.P + (size_t)((g + 1) * G + i) * HW, pb), nb);
+                for (int pos = 0; pos < NK; ++pos) {
+                    const int k = T::kidx[pos / T::KPS][pos % T::KPS];
+                    if (pos + 2 < NK) load_kernel(v[(pos + 2) % 3], pos + 2);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const float m = diffuse_disk(v[pos % 3][0], cs, ncs);
+                    const float sg = diffuse_disk(v[pos % 3][1], cs, ncs);
+                    const float h = diffuse_disk(v[pos % 3][2], cs, ncs);
+                    alpha = alpha && (m > eps) && (sg > eps) && (h > eps);
+                    // once alpha has failed the stores go past the plane (dropped)
+                    const uint32_t oa = alpha ? ob : 0xFFFFFFF0u;
+                    pst_stream(plane(wd.P_out + (size_t)k * HW, pb), oa, m);
+                    pst_stream(plane(wd.P_out + (size_t)(NK + k) * HW, pb), oa, sg);
+                    pst_stream(plane(wd.P_out + (size_t)(2 * NK + k) * HW, pb), oa, h);
+                    // growth summed per source channel, each channel's kernels in
+                    // table order (the order the DFT form's fused step follows)
+                    sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], m, sg, h);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                for (int i = 0; i < G; ++i) {
-                    pd[g * G + i] = diffuse_disk(v[g & 1][i], cs, ncs);
-                    alpha = alpha && (pd[g * G + i] > eps);
-                }
-                __builtin_amdgcn_sched_barrier(0);
             }
-        }
-        // growth summed per source channel, each channel's kernels in table
-        // order (the order the DFT form's fused step follows)
-        if (alpha) {
+            if (!alpha) {
 #pragma unroll
-            for (int s = 0; s < T::C; ++s)
+                for (int c = 0; c < T::C; ++c) sum[c] = 0.f;
 #pragma unroll
-                for (int j = 0; j < T::KPS; ++j) {
-                    const int k = T::kidx[s][j];
-                    sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+                for (int q = 0; q < NP; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, 0.f);
+            }
+        } else {
+            float pd[NP];
+            if (alpha) {
+                // diffuse every gene plane (Section 2.3) and test it against the
+                // cutoff.  The disks are read in groups of G planes, the next
+                // group's reads issued before the current group is reduced, so a
+                // wave has one round trip in flight rather than one per plane (the
+                // scheduling barriers keep the compiler from serialising them again).
+                constexpr int G = (NP % LENIA_GENE_GROUP == 0) ? LENIA_GENE_GROUP : 3, NG = NP / G;
+                static_assert(NP % G == 0, "gene planes come in threes");
+                const NbrB nb = neighbour_bytes(gy, gx, H, W);
+                const float cs = wd.cnt_scale, ncs = wd.cnt_bias;
+                float v[2][G][5];
+#pragma unroll
+                for (int i = 0; i < G; ++i) load_disk(v[0][i], plane(wd.P + (size_t)i * HW, pb), nb);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    if (g + 1 < NG) {
+#pragma unroll
+                        for (int i = 0; i < G; ++i)
+                            load_disk(v[(g + 1) & 1][i], plane(wd.P + (size_t)((g + 1) * G + i) * HW, pb), nb);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int i = 0; i < G; ++i) {
+                        pd[g * G + i] = diffuse_disk(v[g & 1][i], cs, ncs);
+                        alpha = alpha && (pd[g * G + i] > eps);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-        }
+            }
+            // growth summed per source channel, each channel's kernels in table
+            // order (the order the DFT form's fused step follows)
+            if (alpha) {
 #pragma unroll
-        for (int q = 0; q < NP; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
+                for (int s = 0; s < T::C; ++s)
+#pragma unroll
+                    for (int j = 0; j < T::KPS; ++j) {
+                        const int k = T::kidx[s][j];
+                        sum[T::dst[k]] = growth_acc(sum[T::dst[k]], u[k], pd[k], pd[NK + k], pd[2 * NK + k]);
+                    }
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) pst_stream(plane(wd.P_out + (size_t)q * HW, pb), ob, alpha ? pd[q] : 0.f);
+        }
         if (wd.alpha_save) wd.alpha_save[ob >> 2] = alpha ? 1 : 0;
         if (wd.flags_out) {
             float su = 0.f;
@@ -525,7 +573,7 @@ template <class T, int R, int TY, int TX>
 constexpr int tile_lds_floats() { return TileLayout<T, R, TY, TX>::floats; }
 
 // One tile of one world.  Each thread owns Q vertically adjacent cells.
-template <class T, int R, int TY, int TX, bool RINGS = false>
+template <class T, int R, int TY, int TX, bool RINGS = false, bool KMAJOR = true>
 __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int mode, float* sA,
                                              int* tile_flag)
 {
@@ -704,7 +752,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             float a[T::C];
 #pragma unroll
             for (int ch = 0; ch < T::C; ++ch) a[ch] = c[ch * L::CHS + q * L::RS];
-            epilogue_cell<T>(wd, mode, u[q], a, gy + q, gx);
+            epilogue_cell<T, KMAJOR>(wd, mode, u[q], a, gy + q, gx);
         }
     }
 }
@@ -793,7 +841,7 @@ __global__ __launch_bounds__((step_threads<TY, TX>()), LENIA_MIN_WAVES) void ste
 #pragma unroll
     for (int i = 0; i < NW; ++i) words[i] = src[i];
     const WorldArgs wd = __builtin_bit_cast(WorldArgs, words);
-    process_tile<T, R, TY, TX>(wd, tile, mode, sA, &tile_flag);
+    process_tile<T, R, TY, TX, false, false>(wd, tile, mode, sA, &tile_flag);
 }
 
 template <class T, int R, int TY, int TX>
