@@ -105,7 +105,8 @@ struct WorldArgs {
                            // tile in every gene plane (set by a tile that writes its
                            // genes as 0, cleared by one that writes them otherwise)
     const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
-    const float* wt;       // [n_orbits][C][8] the same weights by (orbit, source, slot)
+    const float* wt;       // [n_orbits][wt_stride] the same weights by orbit, packed as
+                           // source * KPS + slot (one scalar load per orbit)
     int H, W;
     int tiles_x, n_tiles;  // tile grid of this world
     float dt;

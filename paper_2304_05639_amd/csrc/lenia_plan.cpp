@@ -28,7 +28,7 @@ WorldArgs WorldPlan::args_template() const
     WorldArgs a;
     std::memset(&a, 0, sizeof(a));
     a.w = d_w;
-    a.wt = d_wt;
+    a.wt = d_wtp;
     a.H = H;
     a.W = W;
     a.dt = (float)dt;
@@ -210,6 +210,22 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
         host_keep.push_back(keep_t);
         hipError_t e0 = hipMemcpyAsync(w.d_wt, keep_t, hwt.size() * sizeof(float),
                                        hipMemcpyHostToDevice, s);
+        if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
+    }
+    // the same weights packed per orbit (source * KPS + slot, stride
+    // wt_stride), so that the step reads an orbit's weights in one scalar load
+    {
+        const int C = w.C, ws = (C * kps == 1) ? 1 : 16;
+        if (C * kps > ws) return set_error(LENIA_ERR_STATE, "packed weight table too small");
+        std::vector<float> hwp((size_t)NO * ws, 0.f);
+        for (int i = 0; i < NO; ++i)
+            for (int sc = 0; sc < C; ++sc)
+                for (int j = 0; j < kps; ++j) hwp[(size_t)i * ws + sc * kps + j] = hwt[((size_t)i * C + sc) * 8 + j];
+        if ((st = dmalloc(p, (void**)&w.d_wtp, hwp.size() * sizeof(float))) != LENIA_OK) return st;
+        float* keep_p = new float[hwp.size()];
+        std::memcpy(keep_p, hwp.data(), hwp.size() * sizeof(float));
+        host_keep.push_back(keep_p);
+        hipError_t e0 = hipMemcpyAsync(w.d_wtp, keep_p, hwp.size() * sizeof(float), hipMemcpyHostToDevice, s);
         if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
     }
     // shell-height coefficients in the same orbit order: [orbit][source][16],

@@ -3,7 +3,8 @@
 //
 // Per output tile (TY x TX cells) a workgroup (one thread per cell, or per
 // vertical pair of cells in tiles of more than 256 cells)
-//   1. stages the tile plus an R-cell halo of every channel of A into LDS
+//   1. stages the tile plus an (R-1)-cell halo of every channel of A into LDS
+//      (every tap has |d| < R, so no offset exceeds R - 1 along either axis)
 //      (wrapped on the torus, so tiny tori accumulate multiply-wrapped taps),
 //      and, where alpha is provably 0 on the whole tile (an empty channel or
 //      a dead gene plane), writes A' = clip01(A), P' = 0 and stops;
@@ -31,7 +32,8 @@ namespace lenia {
 #define LENIA_GENE_GROUP 3  // gene planes per group of disk reads in the epilogue
 #endif
 
-// Layout of the staged tile (TY + 2R rows of TX + 2R positions) in LDS.  A
+// Layout of the staged tile (TY + 2 HALO rows of TX + 2 HALO positions, with
+// HALO = R - 1: the kernels' support is the open disk |d| < R) in LDS.  A
 // position (y, x) starts at float (y * PITCH + x) * ES; its channel s is CHS
 // floats further.  With three channels they are interleaved, one 16-byte
 // vector per position (4th lane zero), so that a tap of every channel is one
@@ -40,16 +42,20 @@ namespace lenia {
 template <class T, int R, int TY, int TX>
 struct TileLayout {
     static constexpr bool interleaved = (T::C == 3);
+    static constexpr int HALO = R - 1;
     static constexpr int ES = interleaved ? 4 : 1;
-    static constexpr int PITCH = interleaved ? (TX + 2 * R) : tile_pitch<R, TX>();
+    static constexpr int PITCH = interleaved ? (TX + 2 * HALO) : tile_pitch<HALO, TX>();
     static constexpr int RS = ES * PITCH;   // floats per row
-    static constexpr int CHS = interleaved ? 1 : (TY + 2 * R) * PITCH;
-    static constexpr int floats = (interleaved ? 4 : T::C) * (TY + 2 * R) * PITCH;
+    static constexpr int CHS = interleaved ? 1 : (TY + 2 * HALO) * PITCH;
+    static constexpr int floats = (interleaved ? 4 : T::C) * (TY + 2 * HALO) * PITCH;
 };
 
-// Kernel weights, per orbit t and source channel s: wt[(t * C + s) * 8 + j] is
-// the weight of the j-th kernel reading channel s (slot order of the table);
-// the index is uniform, so these are scalar loads.
+// Kernel weights, per orbit t and source channel s: wt[t * WS + s * KPS + j]
+// is the weight of the j-th kernel reading channel s (slot order of the
+// table).  The index is uniform: an orbit's weights are one scalar load (16
+// floats with three channels), so the walk waits once per orbit for them.
+template <class T>
+constexpr int wt_stride() { return (T::C * T::KPS == 1) ? 1 : 16; }
 
 // acc[q][s][j] += w[s][j] * sum[q][s]: one orbit's contribution to the
 // potentials of the Q cells, the orbit sum of each source channel times the
@@ -58,11 +64,14 @@ template <class T, int Q>
 __device__ __forceinline__ void orbit_fma(float (&acc)[Q][T::C][T::KPS], const float (&sum)[Q][T::C],
                                           cfloat* w)
 {
+    typedef float wvec __attribute__((ext_vector_type(wt_stride<T>())));
+    typedef const __attribute__((address_space(4))) wvec cwvec;
+    const wvec wv = *(cwvec*)w;
 #pragma unroll
     for (int s = 0; s < T::C; ++s)
 #pragma unroll
         for (int j = 0; j < T::KPS; ++j) {
-            const float wj = w[s * 8 + j];
+            const float wj = wv[s * T::KPS + j];
 #pragma unroll
             for (int q = 0; q < Q; ++q) acc[q][s][j] = fmaf(wj, sum[q][s], acc[q][s][j]);
         }
@@ -113,7 +122,7 @@ template <class T, int Q, int R, class L>
 __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ wt,
                                            float (&u)[Q][T::NK])
 {
-    constexpr int WS = T::C * 8;   // weights per orbit
+    constexpr int WS = wt_stride<T>();   // weights per orbit
     float acc[Q][T::C][T::KPS];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
@@ -579,7 +588,8 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
 {
     using L = TileLayout<T, R, TY, TX>;
     constexpr int NPG = (RINGS ? 9 : 3) * T::NK;   // gene planes
-    constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
+    constexpr int HALO = L::HALO;
+    constexpr int PY = TY + 2 * HALO, PX = TX + 2 * HALO;
     constexpr int NK = T::NK;
     constexpr int NT = step_threads<TY, TX>();
     constexpr int Q = step_cells_per_thread<TY, TX>();
@@ -630,7 +640,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             if (i < NG) {
                 const int yy = i / PX;
                 const int xx = i - yy * PX;
-                int gy = y0 + yy - R, gx = x0 + xx - R;
+                int gy = y0 + yy - HALO, gx = x0 + xx - HALO;
                 if (single_wrap) {
                     gy += (gy < 0) ? H : 0;
                     gy -= (gy >= H) ? H : 0;
@@ -699,7 +709,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
             // empty): alpha = 0 on the tile
             const int ly = Q * (threadIdx.x / TX);
             const int lx = threadIdx.x % TX;
-            write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES, y0 + ly,
+            write_dead_cells<T, Q, L, NPG>(wd, sA + ((ly + HALO) * L::PITCH + (lx + HALO)) * L::ES, y0 + ly,
                                            x0 + lx, (*tile_flag & kGenesZero) == 0);
             if (wd.p_zero != nullptr && threadIdx.x == 0) wd.p_zero[tile] = 1;
             return;
@@ -712,7 +722,7 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
     const int lx = threadIdx.x % TX;
     const int gy = y0 + ly, gx = x0 + lx;
     if (gy >= H || gx >= W) return;
-    const float* c = sA + ((ly + R) * L::PITCH + (lx + R)) * L::ES;
+    const float* c = sA + ((ly + HALO) * L::PITCH + (lx + HALO)) * L::ES;
     if constexpr (RINGS) {
         static_assert(Q == 1 && L::interleaved, "the ring form runs one cell per thread, 3 channels");
         float S[kRings<R>.nre][T::C];
