@@ -273,9 +273,14 @@ template <class T, int NPL, int Q>
 __device__ __forceinline__ void orbit_bwd(float (&g)[Q], float (&v)[Q][T::KPS][3],
                                           const float (&sum)[NPL][Q], cfloat* w, cfloat* bc)
 {
+    // the orbit's 8 weight slots and 16 coefficient slots, each one scalar load
+    typedef float f8v __attribute__((ext_vector_type(8)));
+    typedef float f16v __attribute__((ext_vector_type(16)));
+    const f8v wv = *(const __attribute__((address_space(4))) f8v*)w;
+    const f16v bv = *(const __attribute__((address_space(4))) f16v*)bc;
 #pragma unroll
     for (int j = 0; j < T::KPS; ++j) {
-        const float wj = w[j];
+        const float wj = wv[j];
 #pragma unroll
         for (int q = 0; q < Q; ++q) g[q] = fmaf(wj, sum[j][q], g[q]);
     }
@@ -283,7 +288,7 @@ __device__ __forceinline__ void orbit_bwd(float (&g)[Q], float (&v)[Q][T::KPS][3
     for (int j = 0; j < T::KPS; ++j)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const float c = bc[j * 3 + i];
+            const float c = bv[j * 3 + i];
 #pragma unroll
             for (int q = 0; q < Q; ++q) v[q][j][i] = fmaf(c, sum[NPL - 1][q], v[q][j][i]);
         }
@@ -355,7 +360,9 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
     constexpr int NWV = NTC / 64;
     constexpr int KPS = T::KPS;
     constexpr int NPL = KPS + 1;
-    constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
+    // the kernels' support is |d| < R: an (R - 1)-cell halo covers every tap
+    constexpr int HALO = R - 1;
+    constexpr int PY = TY + 2 * HALO, PX = TX + 2 * HALO;
     using L = GatherLayout<NPL, PY * PX, PX>;
     constexpr int WS = T::C * 8;     // weights per orbit
     constexpr int BS = T::C * 16;    // shell-height coefficients per orbit
@@ -381,7 +388,7 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
 #pragma unroll
     for (int q = 0; q < Q; ++q) valid[q] = (gy + q < H) && (gx < W);
     const int wave = tc / 64, lane = tc % 64;
-    const typename L::Pos c = L::at(sm, (ly + R) * PX + (lx + R));   // the thread's first cell
+    const typename L::Pos c = L::at(sm, (ly + HALO) * PX + (lx + HALO));   // the thread's first cell
 
     const float* src[NPL];
 #pragma unroll
@@ -393,9 +400,9 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
     // 0 and the orbit walk is skipped (the tile's outputs are still written).
     bool kept = true;
     if (b.mode == MODE_LOCAL_UPDATE)
-        kept = stage_planes<L, NPL, R, TY, TX, NT, KPS>(sm, src, H, W, y0, x0, b.alpha);
+        kept = stage_planes<L, NPL, HALO, TY, TX, NT, KPS>(sm, src, H, W, y0, x0, b.alpha);
     else
-        stage_planes<L, NPL, R, TY, TX, NT>(sm, src, H, W, y0, x0);
+        stage_planes<L, NPL, HALO, TY, TX, NT>(sm, src, H, W, y0, x0);
     const bool active = __syncthreads_or(kept) != 0;
     float uc[KPS][Q];
     {

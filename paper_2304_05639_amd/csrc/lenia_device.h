@@ -108,22 +108,22 @@ __device__ __forceinline__ void wrap2(int& gy, int& gx, int H, int W, bool singl
 }
 
 // Stages NPL planes (plane p at src[p], row-major H x W) of the tile whose
-// top-left output cell is (y0, x0), plus an R-cell halo wrapped on the torus,
-// into LDS: the values of position (yy, xx) of the padded tile go to
-// L::store(dst, yy * (TX + 2R) + xx, v).  NT threads, with all of a thread's
-// loads in flight before the LDS writes.
+// top-left output cell is (y0, x0), plus a HALO-cell halo wrapped on the
+// torus, into LDS: the values of position (yy, xx) of the padded tile go to
+// L::store(dst, yy * (TX + 2 HALO) + xx, v).  NT threads, with all of a
+// thread's loads in flight before the LDS writes.
 // The first NM planes are masked: a position whose mask byte is 0 stages 0.
 // Returns whether any of the thread's positions had a nonzero mask byte.
-template <class L, int NPL, int R, int TY, int TX, int NT, int NM = 0>
+template <class L, int NPL, int HALO, int TY, int TX, int NT, int NM = 0>
 __device__ __forceinline__ bool stage_planes(float* dst, const float* const (&src)[NPL], int H,
                                              int W, int y0, int x0,
                                              const uint8_t* mask = nullptr)
 {
     bool any_kept = false;
-    constexpr int PY = TY + 2 * R, PX = TX + 2 * R;
+    constexpr int PY = TY + 2 * HALO, PX = TX + 2 * HALO;
     constexpr int NG = PY * PX;
     constexpr int IT = (NG + NT - 1) / NT;
-    const bool single_wrap = (H >= TY + R) && (W >= TX + R);
+    const bool single_wrap = (H >= TY + HALO + 1) && (W >= TX + HALO + 1);
     plane_t pl[NPL];
 #pragma unroll
     for (int p = 0; p < NPL; ++p) pl[p] = plane(src[p], 4u * (uint32_t)H * (uint32_t)W);
@@ -134,7 +134,7 @@ __device__ __forceinline__ bool stage_planes(float* dst, const float* const (&sr
         if (i < NG) {
             const int yy = i / PX;
             const int xx = i - yy * PX;
-            int gy = y0 + yy - R, gx = x0 + xx - R;
+            int gy = y0 + yy - HALO, gx = x0 + xx - HALO;
             wrap2(gy, gx, H, W, single_wrap);
             const uint32_t o = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
             const bool keep = (NM == 0) || (mask[o] != 0);

@@ -233,6 +233,15 @@ __device__ __forceinline__ float diffuse_staged(const float* g, int c, int hs, f
     return diffuse_disk(v, cs, ncs);
 }
 
+// Height of the cell strips of the fused step: the least h for which a column
+// of ceil(V / h) strips per tile column fits 256 threads.
+constexpr int strip_height(int v)
+{
+    int h = 1;
+    while (((v + h - 1) / h) * v > 256) ++h;
+    return h;
+}
+
 // Torus coordinate of any integer position.
 __device__ __forceinline__ int wrap_any(int v, int n)
 {
@@ -271,7 +280,13 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
     constexpr int HS = V + 2;
     constexpr int NGI = (HS * HS + 255) / 256;      // DMA instructions per wave and plane
     constexpr int GSLOT = 256 * NGI;
-    constexpr int NCR = (V * V + 255) / 256;        // cells per thread
+    // the fused step gives each thread a vertical strip of SH cells of the
+    // V x V tile: column sq, rows p0 .. p0 + SH - 1 (strips of SH rows, the
+    // last one moved up to end at row V - 1, its rows shared with the strip
+    // above left to that one)
+    constexpr int SH = strip_height(V);
+    constexpr int NSG = (V + SH - 1) / SH;          // strips per column
+    static_assert(NSG * V <= 256, "a strip per thread");
     constexpr int XS_E = 2 * DT * XS_P, YT_E = 2 * NB * YT_P, UST_E = 2 * NB * UST_P;
     constexpr int ZC_E = 2 * ZC_ROWS * ZC_P, UT_E = V * V * 4 / (int)sizeof(E);
     constexpr int FWD_E = FUSED ? (XS_E > YT_E ? XS_E : YT_E) : XS_E + YT_E;
@@ -352,15 +367,15 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
 
     // fused step: the per-lane offsets of the staged gene window (DMA
     // instruction i of wave w loads window elements 256 i + 64 w + lane, row
-    // by row from (y0 - 1, x0 - 1) on the torus), and the state of this
-    // thread's cells ci = threadIdx.x + 256 r of the V x V tile: growth sums
-    // per target channel and the position (in the kernel order the tile
-    // follows) where alpha failed, kAlive while it holds, -1 off the world
+    // by row from (y0 - 1, x0 - 1) on the torus), and the state of the SH
+    // cells of this thread's strip: growth sums per target channel and the
+    // position (in the kernel order the tile follows) where alpha failed,
+    // kAlive while it holds, -1 off the world or left to another strip
     const WorldArgs& wd = g.wd;
     constexpr int kAlive = T::NK;
     uint32_t goff[FUSED ? NGI : 1];
-    float gsum[FUSED ? NCR : 1][T::C];
-    int dead_at[FUSED ? NCR : 1];
+    float gsum[FUSED ? SH : 1][T::C];
+    int dead_at[FUSED ? SH : 1];
     if constexpr (FUSED) {
 #pragma unroll
         for (int i = 0; i < NGI; ++i) {
@@ -373,11 +388,13 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
             }
             goff[i] = o;
         }
+        const int sgr = threadIdx.x / V, sq = threadIdx.x - sgr * V;
+        const int p0 = min(SH * sgr, V - SH);
 #pragma unroll
-        for (int r = 0; r < NCR; ++r) {
-            const int ci = threadIdx.x + 256 * r;
-            const int p = ci / V, q = ci - (ci / V) * V;
-            dead_at[r] = (ci < V * V && y0 + p < H && x0 + q < W) ? kAlive : -1;
+        for (int r = 0; r < SH; ++r) {
+            const int p = p0 + r;
+            const bool own = sgr < NSG && p >= SH * sgr;
+            dead_at[r] = (own && y0 + p < H && x0 + sq < W) ? kAlive : -1;
 #pragma unroll
             for (int c = 0; c < T::C; ++c) gsum[r][c] = 0.f;
         }
@@ -670,44 +687,69 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 const plane_t o0 = plane(wd.P_out + (size_t)k * HW, pb);
                 const plane_t o1 = plane(wd.P_out + (size_t)(T::NK + k) * HW, pb);
                 const plane_t o2 = plane(wd.P_out + (size_t)(2 * T::NK + k) * HW, pb);
-                // cell coordinates are formed here from an opaque thread index
-                // (kept across the loop they would take registers the
+                // strip coordinates are formed here from an opaque thread
+                // index (kept across the loop they would take registers the
                 // transforms need)
                 int tid = threadIdx.x;
                 asm volatile("" : "+v"(tid));
-                // the current kernel's genes are in buffer pos & 1
+                const int sgr = tid / V, sq = tid - sgr * V;
+                const int p0 = min(SH * sgr, V - SH);
+                const int cb = (p0 + 1) * HS + sq + 1;     // staged centre of the strip's first cell
+                const float* ub = ut + p0 * V + sq;
+                const uint32_t ob0 = 4u * ((uint32_t)(y0 + p0) * (uint32_t)W + (uint32_t)(x0 + sq));
+                // the current kernel's genes are in buffer pos & 1.  Down the
+                // strip, a cell's upper and centre disk values (and their
+                // counts) are the previous cell's centre and lower ones; the
+                // sums are formed in the per-cell order, so the result is
+                // diffuse_disk's, bitwise.
                 auto cells = [&](const float* gb) {
+                float vu[3], nu[3], vc[3], nc[3];
 #pragma unroll
-                for (int r = 0; r < NCR; ++r) {
+                for (int pl = 0; pl < 3; ++pl) {
+                    vu[pl] = gb[pl * GSLOT + cb - HS];
+                    vc[pl] = gb[pl * GSLOT + cb];
+                    nu[pl] = clip01(fmaf(vu[pl], cs, ncs));
+                    nc[pl] = clip01(fmaf(vc[pl], cs, ncs));
+                }
+#pragma unroll
+                for (int r = 0; r < SH; ++r) {
                     // branch-free: every slot runs the same instructions, and
-                    // the selects keep what alpha allows.  A slot past the
-                    // tile's cells reads cell 0; off the world (dead_at < 0)
-                    // the store offset lies past the plane, so the buffer
-                    // store is dropped.
-                    const int ci0 = tid + 256 * r;
-                    const int ci = (256 * r + 255 < V * V || ci0 < V * V) ? ci0 : 0;
-                    const int p = ci / V, q = ci - (ci / V) * V;
+                    // the selects keep what alpha allows; a slot that is not
+                    // the thread's (dead_at < 0) stores past the plane, where
+                    // the buffer store is dropped
+                    const int c = cb + r * HS;
                     const bool live = dead_at[r] == kAlive;
-                    const float u = ut[ci];
-                    const int c = (p + 1) * HS + q + 1;
-                    const float pd0 = diffuse_staged(gb, c, HS, cs, ncs);
-                    const float pd1 = diffuse_staged(gb + GSLOT, c, HS, cs, ncs);
-                    const float pd2 = diffuse_staged(gb + 2 * GSLOT, c, HS, cs, ncs);
-                    const bool ok = live && (u > eps) && (pd0 > eps) && (pd1 > eps) && (pd2 > eps);
+                    const float u = ub[r * V];
+                    float pd[3];
+#pragma unroll
+                    for (int pl = 0; pl < 3; ++pl) {
+                        const float* gp = gb + pl * GSLOT;
+                        const float vl = gp[c - 1], vr = gp[c + 1], vd = gp[c + HS];
+                        const float nl = clip01(fmaf(vl, cs, ncs)), nr = clip01(fmaf(vr, cs, ncs));
+                        const float nd = clip01(fmaf(vd, cs, ncs));
+                        const float num = (((vu[pl] + vl) + vc[pl]) + vr) + vd;
+                        const float n = (((nu[pl] + nl) + nc[pl]) + nr) + nd;
+                        const float d = clip01(num * __builtin_amdgcn_rcpf(n));
+                        pd[pl] = (n > 0.f) ? d : 0.f;
+                        vu[pl] = vc[pl];
+                        nu[pl] = nc[pl];
+                        vc[pl] = vd;
+                        nc[pl] = nd;
+                    }
+                    const bool ok = live && (u > eps) && (pd[0] > eps) && (pd[1] > eps) && (pd[2] > eps);
                     float cur = gsum[r][0];
 #pragma unroll
                     for (int c3 = 1; c3 < T::C; ++c3) cur = (c3 == dk) ? gsum[r][c3] : cur;
-                    const float gacc = growth_acc(cur, u, pd0, pd1, pd2);
+                    const float gacc = growth_acc(cur, u, pd[0], pd[1], pd[2]);
 #pragma unroll
                     for (int c3 = 0; c3 < T::C; ++c3)
                         gsum[r][c3] = (ok && c3 == dk) ? gacc : gsum[r][c3];
                     dead_at[r] = (live && !ok) ? pos : dead_at[r];
-                    const uint32_t ob = (dead_at[r] >= 0)
-                        ? 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q)) : 0xFFFFFFF0u;
-                    pst_stream(o0, ob, ok ? pd0 : 0.f);
-                    pst_stream(o1, ob, ok ? pd1 : 0.f);
-                    pst_stream(o2, ob, ok ? pd2 : 0.f);
-                    // one cell at a time: hoisting every cell's 15 LDS reads
+                    const uint32_t ob = (dead_at[r] >= 0) ? ob0 + (uint32_t)r * 4u * (uint32_t)W : 0xFFFFFFF0u;
+                    pst_stream(o0, ob, ok ? pd[0] : 0.f);
+                    pst_stream(o1, ob, ok ? pd[1] : 0.f);
+                    pst_stream(o2, ob, ok ? pd[2] : 0.f);
+                    // one cell at a time: hoisting every cell's LDS reads
                     // ahead would take more registers than the wave has
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -723,9 +765,12 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
         asm volatile("" : "+v"(tid));
         // cells whose alpha failed after the first kernel: the gene planes of
         // the kernels before that one hold diffused values, cleared here
+        const int sgr = tid / V, sq = tid - sgr * V;
+        const int p0 = min(SH * sgr, V - SH);
+        const uint32_t ob0 = 4u * ((uint32_t)(y0 + p0) * (uint32_t)W + (uint32_t)(x0 + sq));
         int need = 0;
 #pragma unroll
-        for (int r = 0; r < NCR; ++r) need |= (dead_at[r] > 0 && dead_at[r] < kAlive) ? 1 : 0;
+        for (int r = 0; r < SH; ++r) need |= (dead_at[r] > 0 && dead_at[r] < kAlive) ? 1 : 0;
         if (__any(need)) {
 #pragma unroll 1
             for (int pos = 0; pos + 1 < T::NK; ++pos) {
@@ -734,11 +779,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
                 const plane_t z1 = plane(wd.P_out + (size_t)(T::NK + kk) * HW, pb);
                 const plane_t z2 = plane(wd.P_out + (size_t)(2 * T::NK + kk) * HW, pb);
 #pragma unroll
-                for (int r = 0; r < NCR; ++r) {
+                for (int r = 0; r < SH; ++r) {
                     if (pos < dead_at[r] && dead_at[r] < kAlive) {
-                        const int ci = tid + 256 * r;
-                        const int p = ci / V, q = ci - (ci / V) * V;
-                        const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
+                        const uint32_t ob = ob0 + (uint32_t)r * 4u * (uint32_t)W;
                         pst_stream(z0, ob, 0.f);
                         pst_stream(z1, ob, 0.f);
                         pst_stream(z2, ob, 0.f);
@@ -750,11 +793,9 @@ __global__ __launch_bounds__(256, 2) void dft_conv_kernel(DftArgs g)
         // (one fused multiply-add, as the per-cell epilogue forms it; this
         // file compiles without contraction)
 #pragma unroll
-        for (int r = 0; r < NCR; ++r) {
+        for (int r = 0; r < SH; ++r) {
             if (dead_at[r] < 0) continue;
-            const int ci = tid + 256 * r;
-            const int p = ci / V, q = ci - (ci / V) * V;
-            const uint32_t ob = 4u * ((uint32_t)(y0 + p) * (uint32_t)W + (uint32_t)(x0 + q));
+            const uint32_t ob = ob0 + (uint32_t)r * 4u * (uint32_t)W;
             const bool alive = dead_at[r] == kAlive;
 #pragma unroll
             for (int c = 0; c < T::C; ++c) {
