@@ -50,6 +50,99 @@ struct Orbits {
     static constexpr Tab tab = make();
 };
 
+// ---------------------------------------------------------------------------
+// The kernel core per orbit, at compile time.  A kernel with B shells and
+// heights beta has the tap value beta_i K_C(rho - i), rho = B |d| / R,
+// i = floor(rho) (Section 2.1), K_C(t) = exp(4 - 1 / (t (1 - t))).  So
+//   u_k = (1 / z_k) sum_i beta_{k,i} sum_{o in shell i of B_k} K_C(rho_o - i) S(o)
+// with S(o) the orbit sum of the source channel: the orbits' weighted sums
+// for the six (B, i) pairs of B = 1, 2, 3 serve every kernel, and each kernel
+// combines its B_k of them.  An orbit lies in one shell for each B, so it
+// costs 3 multiply-adds per source channel instead of one per kernel.  The
+// core values depend on R only; they are formed here, in double precision,
+// and rounded to float, so that the step kernel carries them as instruction
+// constants.  The host plan checks them against its own FP64 kernel.
+// Orbits are listed in the step kernel's walk order: axis (a, 0) by a,
+// diagonal (a, a) by a, then general (a, b), 0 < b < a, by a then b.
+// ---------------------------------------------------------------------------
+namespace cx {
+constexpr double sqrt_pos(double x)
+{
+    if (!(x > 0.0)) return 0.0;
+    double y = (x > 1.0) ? x : 1.0;   // Newton's iteration from above
+    for (int i = 0; i < 200; ++i) {
+        const double n = 0.5 * (y + x / y);
+        if (!(n < y)) break;
+        y = n;
+    }
+    return y;
+}
+
+// e^x for x <= 4: x = k ln 2 + f, |f| <= ln 2 / 2 (ln 2 in two parts, so
+// that k ln 2 is exact to about 2^-80), e^f by its Taylor series, times 2^k.
+constexpr double exp_le4(double x)
+{
+    if (x < -800.0) return 0.0;
+    const double ln2_hi = 0.693147180369123816490, ln2_lo = 1.90821492927058770002e-10;
+    const double kf = x * 1.44269504088896340736;
+    const int k = (int)(kf < 0.0 ? kf - 0.5 : kf + 0.5);
+    const double f = (x - k * ln2_hi) - k * ln2_lo;
+    double term = 1.0, sum = 1.0;
+    for (int n = 1; n < 30; ++n) {
+        term *= f / n;
+        sum += term;
+    }
+    for (int n = 0; n < k; ++n) sum *= 2.0;
+    for (int n = 0; n > k; --n) sum *= 0.5;
+    return sum;
+}
+
+constexpr double shell_core(double t)
+{
+    return (t > 0.0 && t < 1.0) ? exp_le4(4.0 - 1.0 / (t * (1.0 - t))) : 0.0;
+}
+}  // namespace cx
+
+// index of the (B, shell i) pair among the six: B = 1: 0; B = 2: 1, 2; B = 3: 3..5
+constexpr int shell_pair(int B, int i) { return B * (B - 1) / 2 + i; }
+
+template <int R>
+struct ShellBasis {
+    static constexpr int NO = Orbits<R>::N;
+    struct Tab {
+        int a[NO], b[NO];
+        int pair[NO][3];      // shell_pair(B, shell of the orbit) for B = 1, 2, 3
+        float core[NO][3];    // K_C at the orbit for B = 1, 2, 3 (0 on a shell boundary)
+    };
+    static constexpr void put(Tab& t, int& n, int a, int b)
+    {
+        t.a[n] = a;
+        t.b[n] = b;
+        const int d2 = a * a + b * b;
+        for (int B = 1; B <= 3; ++B) {
+            // shell i: i^2 R^2 <= B^2 d2 < (i + 1)^2 R^2, in integers
+            int i = 0;
+            while ((i + 1) * (i + 1) * R * R <= B * B * d2) ++i;
+            const double rho = B * cx::sqrt_pos((double)d2) / R;
+            t.pair[n][B - 1] = shell_pair(B, i);
+            t.core[n][B - 1] = (float)cx::shell_core(rho - i);
+        }
+        ++n;
+    }
+    static constexpr Tab make()
+    {
+        Tab t{};
+        int n = 0;
+        for (int a = 1; a < R; ++a) put(t, n, a, 0);
+        for (int a = 1; 2 * a * a < R * R; ++a) put(t, n, a, a);
+        for (int a = 2; a < R; ++a)
+            for (int b = 1; b < a; ++b)
+                if (a * a + b * b < R * R) put(t, n, a, b);
+        return t;
+    }
+    static constexpr Tab tab = make();
+};
+
 inline int orbit_count(int R)
 {
     int n = 0;
@@ -106,7 +199,11 @@ struct WorldArgs {
                            // genes as 0, cleared by one that writes them otherwise)
     const float* w;        // [NK][n_orbits] orbit weights of K~_k (FP32)
     const float* wt;       // [n_orbits][wt_stride] the same weights by orbit, packed as
-                           // source * KPS + slot (one scalar load per orbit)
+                           // source * KPS + slot (one scalar load per orbit); the
+                           // single-kernel table's step reads these
+    const float* shc;      // [C][KPS][8] shell coefficients beta_{k,i} / z_k of slot
+                           // (source, j) at shell_pair(B_k, i), 0 elsewhere; the
+                           // 15-kernel table's step combines the shell sums with these
     int H, W;
     int tiles_x, n_tiles;  // tile grid of this world
     float dt;

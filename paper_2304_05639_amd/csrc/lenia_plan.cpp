@@ -29,6 +29,7 @@ WorldArgs WorldPlan::args_template() const
     std::memset(&a, 0, sizeof(a));
     a.w = d_w;
     a.wt = d_wtp;
+    a.shc = d_shc;
     a.H = H;
     a.W = W;
     a.dt = (float)dt;
@@ -115,6 +116,31 @@ static void free_all(lenia_plan_t p)
     p->capture_stream = nullptr;
     for (void* q : p->allocations) (void)hipFree(q);
     p->allocations.clear();
+}
+
+// The step kernel's compile-time kernel cores (ShellBasis<R>) against the FP64
+// kernel of the plan: for every orbit and B = 1, 2, 3, the unit-height tap of
+// the orbit's shell must round to the compiled value (within one float ulp,
+// for a libm exp that differs in the last bits) and every other shell's must
+// be 0.
+template <int R>
+static bool shell_basis_matches()
+{
+    constexpr auto& t = ShellBasis<R>::tab;
+    for (int o = 0; o < ShellBasis<R>::NO; ++o)
+        for (int B = 1; B <= 3; ++B)
+            for (int i = 0; i < B; ++i) {
+                double unit[3] = {0, 0, 0};
+                unit[i] = 1.0;
+                const double v = raw_kernel_tap(R, B, unit, t.a[o], t.b[o]);
+                const float c = t.core[o][B - 1];
+                if (shell_pair(B, i) != t.pair[o][B - 1]) {
+                    if (v != 0.0) return false;
+                } else if (std::fabs((double)c - v) > std::ldexp(std::fabs(v), -23)) {
+                    return false;
+                }
+            }
+    return true;
 }
 
 // Kernel tables of one world: orbit weights (K~_k at each orbit representative)
@@ -226,6 +252,27 @@ static lenia_status build_world(lenia_plan_t p, const lenia_desc* d, WorldPlan& 
         std::memcpy(keep_p, hwp.data(), hwp.size() * sizeof(float));
         host_keep.push_back(keep_p);
         hipError_t e0 = hipMemcpyAsync(w.d_wtp, keep_p, hwp.size() * sizeof(float), hipMemcpyHostToDevice, s);
+        if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
+    }
+    // the 15-kernel step's shell coefficients: slot (source s, j) of kernel k
+    // with B shells combines the shell sums of B with beta_{k,i} / z_k
+    if (p->table == TABLE_3x15 && (w.R == 12 || w.R == 13)) {
+        if (!(w.R == 12 ? shell_basis_matches<12>() : shell_basis_matches<13>()))
+            return set_error(LENIA_ERR_STATE, "compiled kernel cores differ from the FP64 kernel");
+        std::vector<float> hsc((size_t)Table3x15::C * Table3x15::KPS * 8, 0.f);
+        for (int sc = 0; sc < Table3x15::C; ++sc)
+            for (int j = 0; j < Table3x15::KPS; ++j) {
+                const int k = Table3x15::kidx[sc][j];
+                const int B = w.n_shells[k];
+                const double z = raw_kernel_sum(w.R, B, &w.beta[3 * k]);
+                for (int i = 0; i < B; ++i)
+                    hsc[(size_t)(sc * Table3x15::KPS + j) * 8 + shell_pair(B, i)] = (float)(w.beta[3 * k + i] / z);
+            }
+        if ((st = dmalloc(p, (void**)&w.d_shc, hsc.size() * sizeof(float))) != LENIA_OK) return st;
+        float* keep_c = new float[hsc.size()];
+        std::memcpy(keep_c, hsc.data(), hsc.size() * sizeof(float));
+        host_keep.push_back(keep_c);
+        hipError_t e0 = hipMemcpyAsync(w.d_shc, keep_c, hsc.size() * sizeof(float), hipMemcpyHostToDevice, s);
         if (e0 != hipSuccess) return hip_fail(e0, "uploading kernel tables");
     }
     // shell-height coefficients in the same orbit order: [orbit][source][16],
@@ -370,57 +417,62 @@ static lenia_status autotune(lenia_plan_t p, hipStream_t s)
     if (e == hipSuccess) e = hipEventCreate(&e1);
     for (int c = 0; c < nc && e == hipSuccess; ++c) {
         const int ty = tys[c], tx = txs[c];
+        // the launch arguments of this tile (for a batch, its work list in
+        // device memory), built before the timed region, which holds the
+        // kernel launches alone
+        WorldArgs single{};
+        WorldArgs* dtab = nullptr;
+        int2* ditems = nullptr;
+        int n_items = 0;
+        if (!p->batched) {
+            WorldPlan& w = p->worlds[0];
+            single = w.args_template();
+            single.A = w.ws_A;
+            single.P = (w.mode == MODE_GLOBAL) ? nullptr : w.ws_P;
+            single.A_out = outA[0];
+            single.P_out = outP[0];
+            single.tiles_x = tiles_of(w.W, tx);
+            single.n_tiles = tiles_of(w.H, ty) * single.tiles_x;
+        } else {
+            std::vector<WorldArgs> tab(p->worlds.size());
+            std::vector<int2> items;
+            for (size_t i = 0; i < p->worlds.size(); ++i) {
+                WorldPlan& w = p->worlds[i];
+                WorldArgs a = w.args_template();
+                a.A = w.ws_A;
+                a.P = (w.mode == MODE_GLOBAL) ? nullptr : w.ws_P;
+                a.A_out = outA[i];
+                a.P_out = outP[i];
+                a.tiles_x = tiles_of(w.W, tx);
+                a.n_tiles = tiles_of(w.H, ty) * a.tiles_x;
+                tab[i] = a;
+                for (int t = 0; t < a.n_tiles; ++t) items.push_back(make_int2((int)i, t));
+            }
+            n_items = (int)items.size();
+            e = device_alloc((void**)&dtab, tab.size() * sizeof(WorldArgs));
+            if (e == hipSuccess) e = device_alloc((void**)&ditems, items.size() * sizeof(int2));
+            if (e == hipSuccess)
+                e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(WorldArgs), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(ditems, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+        }
         float ms = 0.f;
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // rep 0 = warm-up
             e = hipEventRecord(e0, s);
             for (int it = 0; it < 3 && e == hipSuccess; ++it) {
                 if (!p->batched) {
-                    WorldPlan& w = p->worlds[0];
-                    WorldArgs a = w.args_template();
-                    a.A = w.ws_A;
-                    a.P = (w.mode == MODE_GLOBAL) ? nullptr : w.ws_P;
-                    a.A_out = outA[0];
-                    a.P_out = outP[0];
-                    a.tiles_x = tiles_of(w.W, tx);
-                    a.n_tiles = tiles_of(w.H, ty) * a.tiles_x;
-                    e = find_step_launcher(p->table, p->R, ty, tx)(a, p->mode, s);
+                    e = find_step_launcher(p->table, p->R, ty, tx)(single, p->mode, s);
                 } else {
-                    // a temporary work list for this tile
-                    std::vector<WorldArgs> tab(p->worlds.size());
-                    std::vector<int2> items;
-                    for (size_t i = 0; i < p->worlds.size(); ++i) {
-                        WorldPlan& w = p->worlds[i];
-                        WorldArgs a = w.args_template();
-                        a.A = w.ws_A;
-                        a.P = (w.mode == MODE_GLOBAL) ? nullptr : w.ws_P;
-                        a.A_out = outA[i];
-                        a.P_out = outP[i];
-                        a.tiles_x = tiles_of(w.W, tx);
-                        a.n_tiles = tiles_of(w.H, ty) * a.tiles_x;
-                        tab[i] = a;
-                        for (int t = 0; t < a.n_tiles; ++t) items.push_back(make_int2((int)i, t));
-                    }
-                    WorldArgs* dtab = nullptr;
-                    int2* ditems = nullptr;
-                    e = device_alloc((void**)&dtab, tab.size() * sizeof(WorldArgs));
-                    if (e == hipSuccess) e = device_alloc((void**)&ditems, items.size() * sizeof(int2));
-                    if (e == hipSuccess)
-                        e = hipMemcpy(dtab, tab.data(), tab.size() * sizeof(WorldArgs), hipMemcpyHostToDevice);
-                    if (e == hipSuccess)
-                        e = hipMemcpy(ditems, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
-                    if (e == hipSuccess) {
-                        BatchList bl{dtab, ditems, (int)items.size()};
-                        e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, s);
-                    }
-                    if (e == hipSuccess) e = hipStreamSynchronize(s);
-                    (void)hipFree(dtab);
-                    (void)hipFree(ditems);
+                    BatchList bl{dtab, ditems, n_items};
+                    e = find_batch_launcher(p->table, p->R, ty, tx)(bl, p->mode, s);
                 }
             }
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         }
+        if (dtab) (void)hipFree(dtab);
+        if (ditems) (void)hipFree(ditems);
         if (e == hipSuccess && ms < best) {
             best = ms;
             bty = ty;

@@ -46,6 +46,7 @@ struct WorldPlan {
     float* d_w = nullptr;          // [NK][n_orbits] orbit weights of K~_k
     float* d_wt = nullptr;         // [n_orbits][C][8] by (orbit, source, slot)
     float* d_wtp = nullptr;        // [n_orbits][wt_stride] packed: source * KPS + slot
+    float* d_shc = nullptr;        // [C][KPS][8] shell coefficients (15-kernel table)
     float* d_bcoef = nullptr;      // [NK][3][n_orbits] beta-gradient coefficients
     float* d_bt = nullptr;         // the same in the step kernel's orbit order
     int* d_nshells = nullptr;      // [NK]

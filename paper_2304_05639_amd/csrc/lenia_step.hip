@@ -181,6 +181,87 @@ __device__ __forceinline__ void conv_cells(const float* c, cfloat* __restrict__ 
             for (int j = 0; j < T::KPS; ++j) u[q][T::kidx[s][j]] = acc[q][s][j];
 }
 
+// The same potentials through the shell sums (ShellBasis): the orbit walk is
+// unrolled at compile time, each orbit's sum (same taps, same pairwise order
+// as conv_cells) enters the (B, shell) sums of B = 1, 2, 3 with the kernel
+// core as an instruction constant, and each kernel then combines six of them
+// with its coefficients (wd.shc).  3 multiply-adds per orbit and channel
+// instead of KPS = 5, and no weight loads in the walk.
+// acc[.][P][.] += k * sum (k = 0 on a shell boundary: nothing to add)
+template <class T, int Q, int P>
+__device__ __forceinline__ void shell_fma(float (&acc)[Q][6][T::C], const float (&sum)[Q][T::C], float k)
+{
+    if (k == 0.f) return;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int s = 0; s < T::C; ++s) acc[q][P][s] = fmaf(k, sum[q][s], acc[q][P][s]);
+}
+
+template <class T, int Q, class L, int R, int I>
+__device__ __forceinline__ void shell_walk(float (&acc)[Q][6][T::C], const float* c)
+{
+    if constexpr (I < ShellBasis<R>::NO) {
+        constexpr auto& t = ShellBasis<R>::tab;
+        constexpr int a = t.a[I], b = t.b[I];
+        constexpr int RS = L::RS, ES = L::ES;
+        float sum[Q][T::C];
+        if constexpr (b == 0) {
+            quad_sum<T, Q, L>(sum, c + a * RS, c - a * RS, c + a * ES, c - a * ES);
+        } else if constexpr (a == b) {
+            quad_sum<T, Q, L>(sum, c + a * (RS + ES), c + a * (RS - ES), c - a * (RS - ES), c - a * (RS + ES));
+        } else {
+            const float* rp = c + a * RS;
+            const float* rm = c - a * RS;
+            const float* cp = c + a * ES;
+            const float* cm = c - a * ES;
+            float s0[Q][T::C], s1[Q][T::C];
+            quad_sum<T, Q, L>(s0, rp + b * ES, rp - b * ES, rm + b * ES, rm - b * ES);
+            quad_sum<T, Q, L>(s1, cp + b * RS, cm + b * RS, cp - b * RS, cm - b * RS);
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+#pragma unroll
+                for (int s = 0; s < T::C; ++s) sum[q][s] = s0[q][s] + s1[q][s];
+        }
+        // constexpr locals: the values become instruction constants (the
+        // table itself is a device global the compiler may not fold)
+        constexpr float k1 = t.core[I][0], k2 = t.core[I][1], k3 = t.core[I][2];
+        shell_fma<T, Q, t.pair[I][0]>(acc, sum, k1);
+        shell_fma<T, Q, t.pair[I][1]>(acc, sum, k2);
+        shell_fma<T, Q, t.pair[I][2]>(acc, sum, k3);
+        shell_walk<T, Q, L, R, I + 1>(acc, c);
+    }
+}
+
+template <class T, int Q, int R, class L>
+__device__ __forceinline__ void conv_cells_shells(const float* c, cfloat* __restrict__ shc,
+                                                  float (&u)[Q][T::NK])
+{
+    float acc[Q][6][T::C];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int p = 0; p < 6; ++p)
+#pragma unroll
+            for (int s = 0; s < T::C; ++s) acc[q][p][s] = 0.f;
+    shell_walk<T, Q, L, R, 0>(acc, c);
+    typedef float f8v __attribute__((ext_vector_type(8)));
+    typedef const __attribute__((address_space(4))) f8v cf8v;
+#pragma unroll
+    for (int s = 0; s < T::C; ++s)
+#pragma unroll
+        for (int j = 0; j < T::KPS; ++j) {
+            const f8v cv = *(cf8v*)(shc + (s * T::KPS + j) * 8);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                float v = cv[0] * acc[q][0][s];
+#pragma unroll
+                for (int p = 1; p < 6; ++p) v = fmaf(cv[p], acc[q][p][s], v);
+                u[q][T::kidx[s][j]] = v;
+            }
+        }
+}
+
 // Gene diffusion, alpha mask, growth and update of one cell (gy, gx) given its
 // potentials u and its current state a[c]; writes A' and P' (and the saved
 // potentials / alpha when requested).
@@ -745,7 +826,10 @@ __device__ __forceinline__ void process_tile(const WorldArgs& wd, int tile, int 
         return;
     }
     float u[Q][NK];
-    conv_cells<T, Q, R, L>(c, (cfloat*)wd.wt, u);
+    if constexpr (T::KPS > 3)
+        conv_cells_shells<T, Q, R, L>(c, (cfloat*)wd.shc, u);
+    else
+        conv_cells<T, Q, R, L>(c, (cfloat*)wd.wt, u);
     if (mode == MODE_POTENTIALS) {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
