@@ -586,21 +586,17 @@ __global__ __launch_bounds__((S * bwd_threads<TY, TX>())) void bwd_gather_kernel
 // ---------------------------------------------------------------------------
 // 3. fixed-order reduction of the per-tile shell-height partials into gbeta
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void bwd_beta_reduce_kernel(const float* part, int n_tiles, int nk,
-                                                             const int* n_shells, float* gbeta)
+// One wave per (k, i): lane l sums tiles l, l + 64, ... in order, then a
+// fixed butterfly across the lanes (no LDS, no block barrier).
+__global__ __launch_bounds__(64) void bwd_beta_reduce_kernel(const float* part, int n_tiles, int nk,
+                                                            const int* n_shells, float* gbeta)
 {
-    __shared__ float red[256];
     const int e = blockIdx.x;           // (k, i)
     const int k = e / 3, i = e - 3 * (e / 3);
     float acc = 0.f;
-    for (int t = threadIdx.x; t < n_tiles; t += 256) acc += part[((size_t)t * nk + k) * 3 + i];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int sft = 128; sft > 0; sft >>= 1) {
-        if (threadIdx.x < sft) red[threadIdx.x] += red[threadIdx.x + sft];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && i < n_shells[k]) gbeta[k * 3 + i] += red[0];
+    for (int t = threadIdx.x; t < n_tiles; t += 64) acc += part[((size_t)t * nk + k) * 3 + i];
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0 && i < n_shells[k]) gbeta[k * 3 + i] += acc;
 }
 
 template <class T, int R, int TY, int TX, int S>
@@ -614,7 +610,7 @@ hipError_t launch_bwd(const BwdArgs& a, const int* d_nshells, float* gbeta, hipS
                        dim3(S * bwd_threads<TY, TX>()), 0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bwd_beta_reduce_kernel, dim3(T::NK * 3), dim3(256), 0, s, a.part, a.n_tiles,
+    hipLaunchKernelGGL(bwd_beta_reduce_kernel, dim3(T::NK * 3), dim3(64), 0, s, a.part, a.n_tiles,
                        T::NK, d_nshells, gbeta);
     return hipGetLastError();
 }
