@@ -9,8 +9,11 @@
 //      and, where alpha is provably 0 on the whole tile (an empty channel or
 //      a dead gene plane), writes A' = clip01(A), P' = 0 and stops;
 //   2. per cell, forms the potentials u_k = K~_k * A_src(k) (Section 2.1) by
-//      summing each lattice-symmetry orbit of taps once per source channel and
-//      multiplying by the orbit weight of each kernel reading that channel;
+//      summing each lattice-symmetry orbit of taps once per source channel,
+//      then either weighting the orbit sum once per kernel reading the channel
+//      (one kernel per channel), or adding it into the channel's six shell
+//      sums (B = 1, 2, 3 shells, compile-time kernel cores) that each kernel
+//      combines with its shell heights (the 15-kernel table);
 //   3. diffuses the 3*NK gene planes with the r_diff = 1 disk (Section 2.3),
 //      forms alpha from the potentials and diffused genes (Section 2.2),
 //      applies the localized growth (Section 2.4) and the clipped dt update,
