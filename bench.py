@@ -600,7 +600,7 @@ def main():
         summarize(leg, fg, wg, window, first, count, args.command)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
+        print(f"bench.py: the library runs on one GPU only (--gpus {args.gpus} requested); "
               "the path shards by domain decomposition, which is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
