@@ -294,6 +294,46 @@ def test_checkpointed_rollout_matches_oracle(L, oracle, conv, tol):
     assert eA <= tol and eP <= tol and eb <= tol
 
 
+@pytest.mark.parametrize("T,ckpt", [(8, 4), (3, 8), (5, 1)])
+def test_rollout_segment_layouts(L, oracle, T, ckpt):
+    """The rollout keeps its last segment from the forward (with the saved
+    buffers) and recomputes the others: segments that divide T evenly, a
+    single segment (nothing recomputed) and one-step segments all give the
+    chained FP64 VJP."""
+    import torch
+    from paper_2304_05639_amd.autograd import rollout
+    w = smooth_world(32, 40, 233)
+    plan = L.Plan(w)
+    A0 = dev(w.A).requires_grad_(True)
+    P0 = dev(w.P).requires_grad_(True)
+    beta = torch.tensor(w.beta, dtype=torch.float32, device="cuda", requires_grad=True)
+    AT, PT = rollout(A0, P0, beta, plan, T=T, ckpt=ckpt)
+    rng = np.random.default_rng(T * 10 + ckpt)
+    gAT = rng.standard_normal(w.A.shape).astype(np.float32)
+    (AT * dev(gAT)).sum().backward()
+    gA, gP, gb = _oracle_rollout_vjp(oracle, w, T, gAT)
+    eA, eP, eb = _rel(host(A0.grad), gA), _rel(host(P0.grad), gP), _rel(host(beta.grad), gb)
+    print(f"rollout T={T} ckpt={ckpt}: rel err gA0 {eA:.2e} gP0 {eP:.2e} gbeta {eb:.2e}")
+    assert eA <= 1e-4 and eP <= 1e-4 and eb <= 1e-4
+
+
+def test_rollout_forward_same_with_and_without_grad(L):
+    """With a gradient wanted, the forward runs its last segment one step at a
+    time with the saved buffers; without, as one multi-step call.  The states
+    are bitwise the same either way, and a second backward-free rollout too."""
+    import torch
+    from paper_2304_05639_amd.autograd import rollout
+    w = inputs.test_world(64, 80, seed=234, n_blobs=5)
+    plan = L.Plan(w)
+    beta = torch.tensor(w.beta, dtype=torch.float32, device="cuda")
+    A0, P0 = dev(w.A), dev(w.P)
+    with torch.no_grad():
+        A1, P1 = rollout(A0, P0, beta, plan, T=10, ckpt=4)
+    A0g, P0g = dev(w.A).requires_grad_(True), dev(w.P).requires_grad_(True)
+    A2, P2 = rollout(A0g, P0g, beta, plan, T=10, ckpt=4)
+    assert torch.equal(A1, A2.detach()) and torch.equal(P1, P2.detach())
+
+
 def _rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
