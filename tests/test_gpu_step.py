@@ -57,6 +57,25 @@ def test_localized_parity_sizes(L, oracle, H, W, seed):
     print(f"{H}x{W}: errA {errA:.2e} errP {errP:.2e} ambiguous {n_amb}")
 
 
+@pytest.mark.parametrize("R,pattern", [(12, (1,)), (12, (2,)), (12, (3,)), (12, (3, 1, 2)), (13, (2, 3))])
+def test_shell_counts(L, oracle, R, pattern):
+    """The step combines per-shell sums for B = 1, 2 and 3 with each kernel's
+    heights: worlds whose kernels all have one shell count, or a fixed mix,
+    each a different set of the six sums in use (heights drawn in (0.1, 1),
+    some of them 0 to leave a shell empty)."""
+    w = inputs.test_world(56, 72, seed=170 + R + len(pattern), n_blobs=6, R=R)
+    rng = np.random.default_rng(7 * R + sum(pattern))
+    for k in range(w.n_shells.shape[0]):
+        b = pattern[k % len(pattern)]
+        w.n_shells[k] = b
+        w.beta[k, :] = 0.0
+        w.beta[k, :b] = rng.uniform(0.1, 1.0, b).astype(np.float32)
+        if b > 1 and k % 4 == 1:
+            w.beta[k, b - 1] = 0.0          # an empty outer shell
+    errA, errP, n_amb = _parity(L, oracle, w)
+    print(f"R={R} shells {pattern}: errA {errA:.2e} errP {errP:.2e} ambiguous {n_amb}")
+
+
 def test_localized_readonly_genes(L, oracle):
     w = inputs.test_world(70, 90, seed=111, n_blobs=6, genotype_update=0)
     _parity(L, oracle, w)
